@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X channelizer path (one JSON line on stdout).
+
+One step = one fe_channelize call over the whole workload: 4 antennas x 2
+pols x 2^24 packed 10-bit samples/pol, 4096 channels, 16 taps, int8
+channel-major output (all six steps of the path), inputs resident in HBM.
+Three input/output buffer sets (about 302 MB each) rotate so no step is
+served from the 256 MB Infinity Cache.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Per-kernel durations come from HIP events the library records on its own
+stream during the timed steps.  The CPU baseline times the FP64 oracle on the
+host over the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
+FP32_PEAK_TFLOPS = 157.3        # MI355X FP32 vector, published
+METRIC = "Gsample/s channelized on 1 GPU (FP32 vs FP16-MFMA) + % HBM roofline"
+PATH_BYTES_PER_SAMPLE = 2.25    # 10-bit in + int8 complex out, per real sample
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in ("paper_2303_09886_amd/csrc/fengine.hip", "include/fengine.h"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_figures(shape: synth.Shape):
+    """Algorithmic bytes and flops per real input sample of each kernel.
+
+    fir:  reads the packed samples (10 bits) once, writes g (float32): 5.25 B;
+          2T flops (T multiply-adds).
+    post: reads g (float32), writes int8 complex for half as many channels as
+          samples: 5 B; n-point complex FFT 5 n log2 n / 2n = 2.5 log2 n,
+          real-FFT untangle ~5, phase + gain + quantise ~9 flops.
+    """
+    n, T = shape.n, shape.taps
+    lg = int(np.log2(n))
+    return {
+        "fir": {"bytes": 1.25 + 4.0, "flops": 2.0 * T},
+        "post": {"bytes": 4.0 + 1.0, "flops": 2.5 * lg + 5.0 + 9.0},
+    }
+
+
+def stored_traffic(kernel: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(w: synth.Workload, spectra: int, threads: int):
+    """Time the FP64 oracle on spectra [0, spectra) of every antenna, split
+    over a thread pool (ctypes releases the GIL)."""
+    import oracle
+    oracle.lib()
+    s = w.shape
+    A = s.antennas
+    per = max(1, -(-spectra * A // threads))
+    tasks = []
+    for a in range(A):
+        for f0 in range(0, spectra, per):
+            tasks.append((a, f0, min(spectra, f0 + per)))
+
+    def run(task):
+        a, f0, f1 = task
+        oracle.channelize(w.raw[a:a + 1], w.total, s.n, s.taps, s.max_delay, w.weights,
+                          w.delays[a:a + 1], w.phases[a:a + 1], w.gains[a:a + 1], f0, f1,
+                          want=("q",))
+        return (f1 - f0) * 2 * 2 * s.n
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        samples = sum(ex.map(run, tasks))
+    dt = time.perf_counter() - t0
+    return {"value": samples / dt / 1e9, "unit": "Gsample/s", "cores": threads, "kind": "oracle",
+            "sample": "spectra 0..%d of all %d antennas x 2 pols of the benchmark workload "
+                      "(%d samples), FP64 C oracle, %d threads" % (spectra - 1, A, samples, threads),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--sets", type=int, default=3, help="rotating input/output buffer sets")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-spectra", type=int, default=None,
+                    help="spectra per antenna for the CPU baseline (default: all)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device copy (for counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this channelizer build has no multi-GPU path "
+              "(antennas are independent; see the sharding notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import paper_2303_09886_amd as fe
+    fe.load_library()
+
+    shape = synth.LARGE
+    N, A, n, S = shape.samples, shape.antennas, shape.n, shape.spectra_per_heap
+    M = N // (2 * n)
+    log("generating workload: %s" % (shape,))
+    w = synth.make_workload(shape, 2)
+
+    dev = torch.device("cuda:0")
+    raw0 = torch.from_numpy(w.raw).to(dev)
+    delays = torch.from_numpy(w.delays).to(dev)
+    phases = torch.from_numpy(w.phases).to(dev)
+    gains = torch.from_numpy(w.gains).to(dev)
+    sets = []
+    for k in range(args.sets):
+        raw = raw0 if k == 0 else torch.roll(raw0, shifts=5 * 977 * k, dims=-1).contiguous()
+        out = torch.empty((A, M // S, n, S, 2, 2), dtype=torch.int8, device=dev)
+        sets.append((raw, out))
+    torch.cuda.synchronize()
+
+    st = fe.Stream(n, shape.taps, A, w.weights, N, spectra_per_heap=S, max_delay=shape.max_delay)
+    log("warmup %d steps" % args.warmup)
+    for i in range(args.warmup):
+        raw, out = sets[i % len(sets)]
+        st.channelize(raw, N, delays, phases, gains, out)
+    torch.cuda.synchronize()
+
+    st.timing(True)
+    log("timing %d steps" % args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        raw, out = sets[i % len(sets)]
+        st.channelize(raw, N, delays, phases, gains, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fir_ms, post_ms, calls = st.timing_read()
+    st.timing(False)
+    status = st.status()
+    st.close()
+    if status != fe.FE_OK:
+        log("warning: stream status %d" % status)
+
+    if args.copy_calibration:
+        a = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    samples = A * 2 * N
+    value = samples / (ms_step * 1e-3) / 1e9
+    fig = kernel_figures(shape)
+    avg = {"fir": fir_ms / max(calls, 1), "post": post_ms / max(calls, 1)}
+    dom = max(avg, key=avg.get)
+    names = {"fir": "fir_kernel<%d>" % 16, "post": "fft_post_kernel<%d>" % n}
+    dur_s = avg[dom] * 1e-3
+    achieved = fig[dom]["bytes"] * samples / dur_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(dom),
+            "kernel": names[dom], "avg_ms": round(avg[dom], 4),
+            "algorithmic_bytes_per_launch": int(fig[dom]["bytes"] * samples),
+            "alu_tflops": round(fig[dom]["flops"] * samples / dur_s / 1e12, 2),
+            "alu_frac_of_fp32_peak": round(fig[dom]["flops"] * samples / dur_s / 1e12 / FP32_PEAK_TFLOPS, 4)}
+    other = "fir" if dom == "post" else "post"
+    kernels = {names[k]: {"avg_ms": round(avg[k], 4),
+                          "GBps": round(fig[k]["bytes"] * samples / (avg[k] * 1e-3) / 1e9, 1)}
+               for k in (dom, other) if avg[k] > 0}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        spectra = M if args.cpu_spectra is None else args.cpu_spectra
+        log("cpu baseline: oracle over %d spectra x %d antennas, %d threads" % (spectra, A, threads))
+        cpu = cpu_baseline(w, spectra, threads)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gsample/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4 antennas x 2 pols, 2^24 packed 10-bit samples/pol per call, "
+                               "4096 channels (8192-pt real FFT), 16-tap PFB, int8 channel-major "
+                               "output in heaps of 256 spectra",
+                   "antennas": A, "pols": 2, "samples_per_pol": N, "channels": n,
+                   "taps": shape.taps, "spectra_per_heap": S, "max_delay": shape.max_delay,
+                   "buffer_sets": args.sets},
+        "hbm_roofline_frac": round(value * PATH_BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * fengine.h -- C ABI of the MI355X (gfx950) F-engine channelizer.
+ *
+ * The library implements the wide-band channelizer data path of Sec. 2.1 of
+ * Merry, "Efficient channelization on a Graphics Processing Unit": for each
+ * polarization of each antenna it unpacks signed 10-bit samples (item 1),
+ * applies the integer coarse delay by choosing where each PFB window is read
+ * (item 2, Sec. 3.3), runs the polyphase filter bank -- the FIR of Eq. (1)
+ * followed by a 2n-point real-to-complex FFT keeping channels 0..n-1 (item 3)
+ * -- rotates each channel by the fine delay and phase (item 4), multiplies by
+ * a complex per-channel gain (item 5), and quantizes to 8-bit signed
+ * Gaussian integers with rounding and saturation, written channel-major
+ * within each output heap of S_h spectra (item 6, Secs. 2.2 and 3.6).
+ *
+ * Conventions (the paper leaves these open; the library fixes them):
+ *  - input: per polarization, a bitstream of 10-bit two's complement
+ *    codes, MSB first, bytes filled MSB first (4 samples = 5 bytes);
+ *  - delays: the total delay d_F (samples) of spectrum F splits into
+ *    c = floor(d) + [d - floor(d) >= 0.5] and tau = d - c in [-0.5, 0.5);
+ *    spectrum F's window is samples [2n(F-T+1) - c, 2n(F+1) - c) of the
+ *    stream (so a call of N samples emits exactly N/(2n) spectra and the
+ *    first T-1 spectra of a stream read zeros before its first sample);
+ *  - w_{t,j} = h[t + 2nj] for the prototype filter h[0 .. 2nT);
+ *  - Y[k] = G[k] * exp(i(phi_F - pi k tau_F / n)) * X[k], X the forward,
+ *    unnormalised FFT;
+ *  - q = clamp(round_half_even(Re/Im Y), -127, 127);
+ *  - output of one call: int8 [A][M/S_h][n][S_h][2 pols][re, im].
+ *
+ * All functions return fe_status (0 on success, < 0 on error); no C++
+ * exception crosses the ABI.  Device pointers are HIP device allocations on
+ * the device that was current when the stream was created; the caller owns
+ * every buffer passed in and must keep it alive until the work enqueued on
+ * the stream's HIP stream has finished.
+ */
+#ifndef FENGINE_H
+#define FENGINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fe_status;
+
+enum {
+    FE_OK = 0,
+    FE_EINVAL = -1,   /* bad argument: null pointer, size not a multiple of
+                         2n*S_h, unsupported n or T, ... (nothing enqueued) */
+    FE_ENOMEM = -2,   /* device allocation failed (fe_stream_create only) */
+    FE_EHIP = -3,     /* a HIP runtime call or kernel launch failed */
+    FE_EDELAY = -4,   /* sticky device-side status: some spectrum's coarse
+                         delay fell outside [0, max_delay] or its delay was
+                         not finite; that polarization's spectrum was written
+                         as zeros.  Reported by fe_stream_status. */
+    FE_ESIZE = -5     /* n_samples larger than the stream's max_samples */
+};
+
+/* Stream configuration, fixed at creation.
+ *   n_channels        n: a power of two, 256 .. 8192
+ *   taps              T: 1 .. 32
+ *   n_antennas        A >= 1; every antenna has two polarizations
+ *   spectra_per_heap  S_h >= 1 (256 in the paper, Sec. 2.2)
+ *   max_delay         D_max >= 0, largest coarse delay accepted (samples)
+ *   max_samples       largest N (samples per polarization) of one call,
+ *                     a multiple of 2n*S_h, at most 2^28; sizes the
+ *                     library's workspace (A*2*max_samples*4 bytes)
+ *   weights           HOST pointer to float32[2n*T], the prototype filter h;
+ *                     copied to the device during fe_stream_create */
+typedef struct fe_config {
+    int32_t n_channels;
+    int32_t taps;
+    int32_t n_antennas;
+    int32_t spectra_per_heap;
+    int32_t max_delay;
+    int32_t reserved0;            /* must be 0 */
+    int64_t max_samples;
+    const float *weights;
+} fe_config;
+
+/* Opaque per-stream state owned by the library: the last
+ * 2n(T-1)+D_max samples of every polarization (the overlap of Sec. 3.1,
+ * enlarged for delay changes as in Sec. 3.3), the device copy of the
+ * weights, the workspace and the sticky status word. */
+typedef struct fe_stream fe_stream;
+
+/* Create a stream whose work is enqueued on `hip_stream` (a hipStream_t,
+ * NULL for the default stream).  The history starts as zeros (samples before
+ * the stream's first sample read as zero).  Allocates device memory and
+ * synchronizes once; *out is set only on success. */
+fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **out);
+
+/* Release a stream (synchronizes its HIP stream first).  NULL is accepted. */
+fe_status fe_stream_destroy(fe_stream *s);
+
+/* Change the HIP stream later calls are enqueued on. */
+fe_status fe_stream_set_hip_stream(fe_stream *s, void *hip_stream);
+
+/* Enqueue: zero the history, clear the sticky status, restart at sample 0. */
+fe_status fe_stream_reset(fe_stream *s);
+
+/* Channelize the next N samples of every polarization (Sec. 2.1, items 1-6).
+ *   raw     device uint8 [A][2][N*5/4]: the packed samples of this call,
+ *           continuing where the previous call of this stream stopped
+ *   n_samples  N > 0, a multiple of 2n*S_h, <= max_samples
+ *   delays  device float64 [A][2][M], M = N/(2n): total delay d_F (samples)
+ *           of each spectrum of this call
+ *   phases  device float64 [A][2][M]: phase phi_F (radians)
+ *   gains   device float32 [A][2][n][2]: complex gain (re, im) per channel
+ *   out     device int8 [A][M/S_h][n][S_h][2][2]
+ * Enqueues the work and returns without synchronizing and without
+ * allocating.  Not safe to call on one fe_stream from two host threads at
+ * once.  On FE_EINVAL/FE_ESIZE nothing is enqueued and the stream state is
+ * unchanged. */
+fe_status fe_channelize(fe_stream *s, const uint8_t *raw, int64_t n_samples,
+                        const double *delays, const double *phases,
+                        const float *gains, int8_t *out);
+
+/* The same call with the pre-quantisation spectra as output:
+ *   y_out   device float32 [A][2][M][n][2] = Y (complex64)
+ * Identical kernels, identical state update; only the final store differs. */
+fe_status fe_channelize_prequant(fe_stream *s, const uint8_t *raw, int64_t n_samples,
+                                 const double *delays, const double *phases,
+                                 const float *gains, float *y_out);
+
+/* The same call stopped after the FIR (Eq. (1)):
+ *   g_out   device float32 [A][2][M][2n], the filtered samples g of every
+ *           spectrum (zeros where the delay was out of range).
+ * Updates the stream state exactly as fe_channelize does. */
+fe_status fe_channelize_fir(fe_stream *s, const uint8_t *raw, int64_t n_samples,
+                            const double *delays, float *g_out);
+
+/* Synchronize the stream's HIP stream and return its sticky status:
+ * FE_OK, FE_EDELAY (cleared only by fe_stream_reset), or FE_EHIP. */
+fe_status fe_stream_status(fe_stream *s);
+
+/* Kernel timing for measurement tools.  While enabled, every call records
+ * HIP events on its HIP stream around its kernels (no synchronization, no
+ * device allocation; events are created by fe_stream_timing(s, 1), at most
+ * 4096 calls are recorded between reads).  fe_stream_timing_read
+ * synchronizes and returns, over the calls recorded since timing was enabled
+ * or last read, the summed milliseconds of the FIR kernel (steps 1-3a) and of
+ * the FFT/post-processing kernel (steps 3b-6) and the number of calls, then
+ * starts a new accumulation.  Any pointer may be NULL. */
+fe_status fe_stream_timing(fe_stream *s, int enable);
+fe_status fe_stream_timing_read(fe_stream *s, double *fir_ms, double *post_ms, int64_t *calls);
+
+/* Test hook for step 1 alone: unpack samples [first, first+count) of the
+ * packed stream `raw` (device, at least (first+count)*10/8 rounded up bytes)
+ * into int32 `out` (device) with the library's device unpacker, on
+ * `hip_stream`.  first and count >= 0. */
+fe_status fe_debug_unpack10(const uint8_t *raw, int64_t first, int64_t count,
+                            int32_t *out, void *hip_stream);
+
+/* Human-readable text of a status code (static storage). */
+const char *fe_strerror(fe_status status);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t fe_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FENGINE_H */

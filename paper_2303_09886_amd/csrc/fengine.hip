@@ -1,0 +1,964 @@
+// fengine.hip -- MI355X (gfx950) F-engine channelizer: kernels and C ABI.
+//
+// Data path (Sec. 2.1 of Merry, "Efficient channelization on a Graphics
+// Processing Unit"), per polarization of each antenna:
+//   1. unpack signed 10-bit samples                       (item 1, Sec. 2.2)
+//   2. coarse delay = choice of where each window is read (item 2, Sec. 3.3)
+//   3. PFB: FIR of Eq. (1), 2n-point real FFT, keep n bins (item 3)
+//   4. fine delay as a per-channel phase rotation         (item 4, Sec. 3.6)
+//   5. complex per-channel gain                           (item 5)
+//   6. int8 quantisation, channel-major heaps             (item 6, Sec. 3.6)
+//
+// Two kernels per call:
+//   fir_kernel      steps 1-3a.  One thread per FIR column t (Sec. 3.4: the
+//                   input viewed as a 2n-wide matrix, column t filtered with
+//                   weights w_t), sliding over a run of consecutive spectra
+//                   with the window held in registers, so every packed
+//                   sample is unpacked about once.  Writes float32 g.
+//   fft_post_kernel steps 3b-6.  One workgroup per (antenna, spectrum): both
+//                   polarizations' n-point complex FFTs (even/odd samples as
+//                   re/im, the real-input technique of Sec. 4.1) in LDS with
+//                   radix-16 Stockham passes, the real-FFT untangle, phase,
+//                   gain, half-even rounding with saturation and the
+//                   channel-major store.
+// plus a small history copy: the last H = 2n(T-1)+D_max samples of every
+// polarization stay on the device for the next call (the chunk overlap of
+// Sec. 3.1 sized for delay changes as in Sec. 3.3).
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fengine.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Small complex helpers (float2 = re, im)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+// multiply by -i
+__device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
+
+// ---------------------------------------------------------------------------
+// Step 1: sample j (>= 0) of a packed, MSB-first 10-bit two's complement
+// stream.  The 10 bits of a sample lie in bytes 5j/4 and 5j/4 + 1, starting
+// at bit offset (10j) mod 8 = 2 (j mod 4) from the MSB.  Valid for
+// j < 2^32 / 5.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int sample10(const uint8_t *__restrict__ p, uint32_t j)
+{
+    const uint32_t byte = (5u * j) >> 2;
+    const uint32_t sh = (j & 3u) << 1;
+    const uint32_t v = (uint32_t(p[byte]) << 8) | uint32_t(p[byte + 1]);
+    return int32_t(v << (16u + sh)) >> 22;          // sign-extend the 10-bit field
+}
+
+// Sample at index i relative to the first sample of this call: i < 0 reads
+// the history buffer, which holds the H samples preceding the call.
+__device__ __forceinline__ int sample_at(const uint8_t *__restrict__ chunk,
+                                         const uint8_t *__restrict__ hist,
+                                         int64_t i, int H)
+{
+    return i >= 0 ? sample10(chunk, uint32_t(i)) : sample10(hist, uint32_t(i + H));
+}
+
+// ---------------------------------------------------------------------------
+// Steps 2 and 4: split of the total delay d (float64) into the coarse integer
+// c and the fine residual tau = d - c in [-0.5, 0.5):
+//   c = floor(d) + [d - floor(d) >= 0.5]; valid iff d finite and 0 <= c <= D.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool split_delay(double d, int D, int &c, double &tau)
+{
+    c = 0;
+    tau = 0.0;
+    // -0.5 <= d < D + 0.5 is exactly 0 <= c <= D and rejects NaN and inf
+    if (!(d >= -0.5 && d < double(D) + 0.5))
+        return false;
+    const double whole = floor(d);
+    const double frac = d - whole;
+    const double cc = frac >= 0.5 ? whole + 1.0 : whole;
+    c = int(cc);
+    tau = d - cc;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1: unpack + coarse delay + FIR (Eq. (1)).
+//
+// Thread = one column t of one stream (antenna, pol) for a run of R <= 64
+// consecutive spectra.  g_{F,t} = sum_j s[2n(F-T+1) - c_F + t + 2nj] h[t+2nj].
+// For consecutive spectra with the same c the window rows shift by one, so
+// one new sample is unpacked per spectrum; a change of c reloads the window.
+// The delay split of spectrum m0+l is computed by lane l and broadcast with
+// readlane (wave-uniform), so c is an SGPR in the hot loop.
+// ---------------------------------------------------------------------------
+
+constexpr int FIR_THREADS = 256;
+
+template <int T>
+__global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
+    const uint8_t *__restrict__ raw, int64_t raw_stride,
+    const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
+    const float *__restrict__ taps, const double *__restrict__ delays,
+    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs)
+{
+    const int b = blockIdx.x;
+    const int cb = b % colblocks;
+    const int rest = b / colblocks;
+    const int run = rest % runs;
+    const int s = rest / runs;
+    const int t = cb * FIR_THREADS + threadIdx.x;
+    const int m0 = run * R;
+    const int mend = min(m0 + R, M);
+
+    float h[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j)
+        h[j] = taps[t + n2 * j];
+
+    const int lane = threadIdx.x & 63;
+    int c_lane = 0, ok_lane = 0;
+    if (m0 + lane < mend) {
+        double tau;
+        ok_lane = split_delay(delays[int64_t(s) * M + m0 + lane], D, c_lane, tau) ? 1 : 0;
+    }
+
+    const uint8_t *rs = raw + int64_t(s) * raw_stride;
+    const uint8_t *hs = hist + int64_t(s) * hist_stride;
+    float *gs = g + int64_t(s) * M * n2 + t;
+
+    float w[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j)
+        w[j] = 0.f;
+    int c_prev = -1;
+
+    for (int m = m0; m < mend; m += T) {
+#pragma unroll
+        for (int r = 0; r < T; ++r) {
+            const int mm = m + r;
+            if (mm < mend) {
+                const int c = __builtin_amdgcn_readlane(c_lane, mm - m0);
+                const int ok = __builtin_amdgcn_readlane(ok_lane, mm - m0);
+                // index of window row j = 0, relative to this call's first sample
+                const int64_t base = int64_t(n2) * (mm - T + 1) - c + t;
+                if (c != c_prev) {
+#pragma unroll
+                    for (int j = 0; j < T; ++j)
+                        w[(r + j) % T] = float(sample_at(rs, hs, base + int64_t(n2) * j, H));
+                    c_prev = c;
+                } else {
+                    w[(r + T - 1) % T] = float(sample_at(rs, hs, base + int64_t(n2) * (T - 1), H));
+                }
+                float acc = 0.f;
+#pragma unroll
+                for (int j = 0; j < T; ++j)
+                    acc = fmaf(w[(r + j) % T], h[j], acc);
+                gs[int64_t(mm) * n2] = ok ? acc : 0.f;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FFT building blocks: in-register DFTs of size 2, 4, 8, 16 (forward,
+// exp(-2 pi i m k / R)), natural order in and out.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void dft2(float2 &a, float2 &b)
+{
+    const float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+__device__ __forceinline__ void dft4(float2 &x0, float2 &x1, float2 &x2, float2 &x3)
+{
+    const float2 s02 = cadd(x0, x2), d02 = csub(x0, x2);
+    const float2 s13 = cadd(x1, x3), d13 = cmul_mi(csub(x1, x3));
+    x0 = cadd(s02, s13);
+    x2 = csub(s02, s13);
+    x1 = cadd(d02, d13);
+    x3 = csub(d02, d13);
+}
+
+constexpr float kR2 = 0.70710678118654752440f;     // cos(pi/4)
+constexpr float kC8 = 0.92387953251128675613f;     // cos(pi/8)
+constexpr float kS8 = 0.38268343236508977173f;     // sin(pi/8)
+
+template <int R> struct Dft;
+
+template <> struct Dft<2> {
+    __device__ static void run(float2 *x) { dft2(x[0], x[1]); }
+};
+
+template <> struct Dft<4> {
+    __device__ static void run(float2 *x) { dft4(x[0], x[1], x[2], x[3]); }
+};
+
+// 8 = 4 x 2: m = 2 m1 + m2, k = k1 + 4 k2
+template <> struct Dft<8> {
+    __device__ static void run(float2 *x)
+    {
+        float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+        float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+        dft4(e0, e1, e2, e3);
+        dft4(o0, o1, o2, o3);
+        // twiddle W8^k1 on the odd half
+        o1 = make_float2(kR2 * (o1.x + o1.y), kR2 * (o1.y - o1.x));
+        o2 = cmul_mi(o2);
+        o3 = make_float2(kR2 * (o3.y - o3.x), -kR2 * (o3.x + o3.y));
+        x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
+        x[1] = cadd(e1, o1); x[5] = csub(e1, o1);
+        x[2] = cadd(e2, o2); x[6] = csub(e2, o2);
+        x[3] = cadd(e3, o3); x[7] = csub(e3, o3);
+    }
+};
+
+// 16 = 4 x 4: m = 4 m1 + m2, k = k1 + 4 k2
+template <> struct Dft<16> {
+    __device__ static void run(float2 *x)
+    {
+#pragma unroll
+        for (int m2 = 0; m2 < 4; ++m2)
+            dft4(x[m2], x[m2 + 4], x[m2 + 8], x[m2 + 12]);     // -> y[m2][k1] at x[m2 + 4 k1]
+        // twiddles W16^(m2 k1)
+        const float2 w1 = make_float2(kC8, -kS8), w2 = make_float2(kR2, -kR2), w3 = make_float2(kS8, -kC8);
+        x[5] = cmul(x[5], w1);                       // m2=1,k1=1
+        x[9] = cmul(x[9], w2);                       // m2=1,k1=2
+        x[13] = cmul(x[13], w3);                     // m2=1,k1=3
+        x[6] = cmul(x[6], w2);                       // m2=2,k1=1
+        x[10] = cmul_mi(x[10]);                      // m2=2,k1=2 (W^4)
+        x[14] = cmul(x[14], make_float2(-kR2, -kR2));    // m2=2,k1=3 (W^6)
+        x[7] = cmul(x[7], w3);                       // m2=3,k1=1 (W^3)
+        x[11] = cmul(x[11], make_float2(-kR2, -kR2));    // m2=3,k1=2 (W^6)
+        x[15] = cmul(x[15], make_float2(-kC8, kS8));     // m2=3,k1=3 (W^9)
+        float2 y[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 a = x[4 * k1], b = x[4 * k1 + 1], c = x[4 * k1 + 2], d = x[4 * k1 + 3];
+            dft4(a, b, c, d);                        // over m2 -> k2
+            y[k1] = a; y[k1 + 4] = b; y[k1 + 8] = c; y[k1 + 12] = d;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            x[i] = y[i];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// FFT plans: radices in execution order; n = product.  Threads per
+// polarization = n/16, each owning 16 points (16/R butterflies per pass).
+// ---------------------------------------------------------------------------
+
+template <int N> struct Plan;
+template <> struct Plan<256>  { static constexpr int P = 2; static constexpr int R[4] = {16, 16, 1, 1}; };
+template <> struct Plan<512>  { static constexpr int P = 3; static constexpr int R[4] = {16, 16, 2, 1}; };
+template <> struct Plan<1024> { static constexpr int P = 3; static constexpr int R[4] = {16, 16, 4, 1}; };
+template <> struct Plan<2048> { static constexpr int P = 3; static constexpr int R[4] = {16, 16, 8, 1}; };
+template <> struct Plan<4096> { static constexpr int P = 3; static constexpr int R[4] = {16, 16, 16, 1}; };
+template <> struct Plan<8192> { static constexpr int P = 4; static constexpr int R[4] = {16, 16, 16, 2}; };
+
+// Host and device agree on the twiddle-table layout: for each pass p with
+// L_p = R_0 ... R_{p-1} > 1, a block [L_p][R_p - 1] of exp(-2 pi i j q / (L_p R_p)).
+template <int N>
+__host__ __device__ constexpr int tw_offset(int p)
+{
+    int off = 0, L = 1;
+    for (int i = 0; i < p; ++i) {
+        if (L > 1)
+            off += L * (Plan<N>::R[i] - 1);
+        L *= Plan<N>::R[i];
+    }
+    return off;
+}
+
+template <int N>
+__host__ __device__ constexpr int tw_L(int p)
+{
+    int L = 1;
+    for (int i = 0; i < p; ++i)
+        L *= Plan<N>::R[i];
+    return L;
+}
+
+// One Stockham pass (radix R, L = product of earlier radices) over one
+// polarization's n points held in LDS (or, for the first pass, read straight
+// from the float32 g of this spectrum: z[m] = g[2m] + i g[2m+1]).
+//   butterfly b: inputs z[b + q n/R], twiddle exp(-2 pi i j q/(L R)) with
+//   j = b mod L, R-point DFT, outputs to (b - j) R + j + r L.
+template <int N, int R, int L, bool FIRST>
+__device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, const float2 *__restrict__ src,
+                                         int tp, const float2 *__restrict__ tw)
+{
+    constexpr int NB = N / R;              // butterflies per polarization
+    constexpr int NTP = N / 16;            // threads per polarization
+    constexpr int PER = NB / NTP;          // butterflies per thread
+    float2 v[PER][R];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int b = tp + u * NTP;
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            v[u][q] = FIRST ? src[b + q * NB] : buf[b + q * NB];
+    }
+    if (!FIRST)
+        __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int b = tp + u * NTP;
+        const int j = b % L;
+        if (L > 1) {
+#pragma unroll
+            for (int q = 1; q < R; ++q)
+                v[u][q] = cmul(v[u][q], tw[j * (R - 1) + q - 1]);
+        }
+        Dft<R>::run(v[u]);
+        const int base = (b - j) * R + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            buf[base + r * L] = v[u][r];
+    }
+    __syncthreads();
+}
+
+template <int N, int P>
+__device__ __forceinline__ void fft_run(float2 *buf, const float2 *src, int tp, const float2 *tw_all)
+{
+    if constexpr (P < Plan<N>::P) {
+        constexpr int R = Plan<N>::R[P];
+        constexpr int L = tw_L<N>(P);
+        fft_pass<N, R, L, P == 0>(buf, src, tp, tw_all + tw_offset<N>(P));
+        fft_run<N, P + 1>(buf, src, tp, tw_all);
+    }
+}
+
+// Wavefront dispatch sends workgroup b to XCD b mod 8.  Map it to a logical
+// index so that each XCD works on one contiguous range of logical indices:
+// consecutive spectra of an antenna then share an L2, which merges their
+// partial writes into the same output lines.
+__device__ __forceinline__ int xcd_logical(int b, int G)
+{
+    constexpr int X = 8;
+    const int xcd = b % X, local = b / X;
+    const int per = (G + X - 1) / X;
+    int full = G % X;
+    if (full == 0)
+        full = X;
+    return xcd < full ? xcd * per + local : full * per + (xcd - full) * (per - 1) + local;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2: FFT + R2C untangle + fine delay/phase + gain + quantise + store.
+// One workgroup = (antenna a, spectrum F), n/8 threads: threads [0, n/16)
+// transform polarization 0, the rest polarization 1.
+// ---------------------------------------------------------------------------
+
+enum { OUT_INT8 = 0, OUT_PREQUANT = 1 };
+
+template <int N, int MODE>
+__global__ __launch_bounds__(N / 8) void fft_post_kernel(
+    const float *__restrict__ g, const double *__restrict__ delays,
+    const double *__restrict__ phases, const float2 *__restrict__ gains,
+    const float2 *__restrict__ tw_all, const float2 *__restrict__ untangle,
+    int8_t *__restrict__ out, float2 *__restrict__ y_out, int *__restrict__ status,
+    int M, int S, int D)
+{
+    constexpr int NT = N / 8;
+    constexpr int NTP = N / 16;
+    constexpr int NH = N / 64;             // coarse phase-table entries (k >> 6)
+    __shared__ float2 buf[2 * N];
+    __shared__ float2 ph_hi[2][NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[2][64];
+
+    const int logical = xcd_logical(blockIdx.x, gridDim.x);
+    const int a = logical / M;
+    const int F = logical % M;
+    const int tid = threadIdx.x;
+    const int pol = tid / NTP;
+    const int tp = tid % NTP;
+
+    // delay split and phase of both polarizations (wave-uniform work)
+    int c0, c1;
+    double tau0, tau1;
+    const int64_t sp0 = (int64_t(a) * 2 + 0) * M + F, sp1 = (int64_t(a) * 2 + 1) * M + F;
+    const bool ok0 = split_delay(delays[sp0], D, c0, tau0);
+    const bool ok1 = split_delay(delays[sp1], D, c1, tau1);
+    if ((!ok0 || !ok1) && tid == 0)
+        atomicOr(status, 1);
+
+    // phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] * ph_lo[k & 63];
+    // arguments in revolutions, reduced in float64, sin/cos in float32.
+    {
+        constexpr double inv_two_pi = 0.15915494309189533577;
+        for (int e = tid; e < 2 * (NH + 64); e += NT) {
+            const int p = e / (NH + 64);
+            const int i = e % (NH + 64);
+            const double tau = p ? tau1 : tau0;
+            const double phi = phases[p ? sp1 : sp0];
+            double rev;
+            if (i < NH)
+                rev = phi * inv_two_pi - double(64 * i) * tau / double(2 * N);
+            else
+                rev = -double(i - NH) * tau / double(2 * N);
+            rev -= rint(rev);
+            float sn, cs;
+            sincospif(float(2.0 * rev), &sn, &cs);
+            if (i < NH)
+                ph_hi[p][i] = make_float2(cs, sn);
+            else
+                ph_lo[p][i - NH] = make_float2(cs, sn);
+        }
+    }
+
+    // forward n-point complex FFT of z[m] = g[2m] + i g[2m+1] per polarization
+    const float2 *src = reinterpret_cast<const float2 *>(g + ((int64_t(a) * 2 + pol) * M + F) * (2 * N));
+    fft_run<N, 0>(buf + pol * N, src, tp, tw_all);
+
+    // post-processing: thread owns channels k = tid + NT i for both pols
+    const float2 *gain0 = gains + (int64_t(a) * 2 + 0) * N;
+    const float2 *gain1 = gains + (int64_t(a) * 2 + 1) * N;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = tid + NT * i;
+        const int km = (N - k) & (N - 1);
+        const float2 w = untangle[k];                 // exp(-i pi k / n)
+        float2 Y[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const float2 zk = buf[p * N + k];
+            const float2 zm = buf[p * N + km];
+            // E = (Z[k] + conj Z[n-k]) / 2, O = (Z[k] - conj Z[n-k]) / (2i)
+            const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            const float2 O = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+            const float2 X = cadd(E, cmul(w, O));
+            const float2 rot = cmul(ph_hi[p][k >> 6], ph_lo[p][k & 63]);
+            const float2 gk = (p ? gain1 : gain0)[k];
+            const bool ok = p ? ok1 : ok0;
+            Y[p] = ok ? cmul(gk, cmul(rot, X)) : make_float2(0.f, 0.f);
+        }
+        if (MODE == OUT_PREQUANT) {
+            y_out[((int64_t(a) * 2 + 0) * M + F) * N + k] = Y[0];
+            y_out[((int64_t(a) * 2 + 1) * M + F) * N + k] = Y[1];
+        } else {
+            uint32_t word = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float v = (e & 1) ? Y[e >> 1].y : Y[e >> 1].x;
+                const float q = fminf(fmaxf(rintf(v), -127.f), 127.f);   // half-even, saturate
+                word |= (uint32_t(int32_t(q)) & 0xFFu) << (8 * e);
+            }
+            const int64_t idx = ((int64_t(a) * (M / S) + F / S) * N + k) * S + (F % S);
+            reinterpret_cast<uint32_t *>(out)[idx] = word;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// History maintenance and small helpers
+// ---------------------------------------------------------------------------
+
+// For every stream s: dst[s*dst_stride + dst_off + i] = src[s*src_stride + src_off + i], i < bytes.
+__global__ void copy_rows_kernel(uint8_t *__restrict__ dst, int64_t dst_stride, int64_t dst_off,
+                                 const uint8_t *__restrict__ src, int64_t src_stride, int64_t src_off,
+                                 int64_t bytes, int streams)
+{
+    const int64_t total = bytes * streams;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t s = e / bytes, i = e % bytes;
+        dst[s * dst_stride + dst_off + i] = src[s * src_stride + src_off + i];
+    }
+}
+
+__global__ void fill_zero_kernel(uint8_t *__restrict__ p, int64_t bytes, int *__restrict__ status)
+{
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < bytes;
+         e += int64_t(gridDim.x) * blockDim.x)
+        p[e] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *status = 0;
+}
+
+__global__ void unpack_kernel(const uint8_t *__restrict__ raw, int64_t first, int64_t count,
+                              int32_t *__restrict__ out)
+{
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t j = first + e;
+        // 64-bit safe form of sample10 for arbitrary offsets
+        const int64_t bit = 10 * j;
+        const uint32_t v = (uint32_t(raw[bit >> 3]) << 8) | uint32_t(raw[(bit >> 3) + 1]);
+        out[e] = int32_t(v << (16u + uint32_t(bit & 7))) >> 22;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct fe_stream {
+    int n, T, Tk, A, S, D, H;
+    int64_t max_samples;
+    int device;
+    hipStream_t stream;
+    float *d_taps;          // [2n*Tk], zero-padded in front when Tk > T
+    float2 *d_tw;           // FFT twiddle blocks
+    float2 *d_untangle;     // exp(-i pi k / n)
+    uint8_t *d_hist;        // [A*2][H*5/4]
+    uint8_t *d_hist_tmp;    // same, used when a call is shorter than H
+    float *d_g;             // [A*2][max_samples/(2n)][2n]
+    int *d_status;
+    // kernel timing (fe_stream_timing): 4 events per recorded call
+    std::vector<hipEvent_t> ev;
+    int ev_used;            // calls recorded since the last read
+    bool timing;
+};
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int kernel_taps(int T)
+{
+    static const int sup[] = {4, 8, 16, 24, 32};
+    for (int t : sup)
+        if (T <= t)
+            return t;
+    return -1;
+}
+
+template <int N>
+std::vector<float2> make_twiddles()
+{
+    std::vector<float2> tw(size_t(tw_offset<N>(Plan<N>::P)) + 1);
+    for (int p = 0; p < Plan<N>::P; ++p) {
+        const int L = tw_L<N>(p), R = Plan<N>::R[p];
+        if (L == 1)
+            continue;
+        const int off = tw_offset<N>(p);
+        for (int j = 0; j < L; ++j)
+            for (int q = 1; q < R; ++q) {
+                // exp(-2 pi i j q / (L R)) from an exact integer angle index
+                const long double a = -2.0L * 3.141592653589793238462643383279503L
+                                      * (long double)((int64_t)j * q) / (long double)(L * R);
+                tw[size_t(off) + size_t(j) * (R - 1) + (q - 1)] =
+                    make_float2(float(std::cos(a)), float(std::sin(a)));
+            }
+    }
+    return tw;
+}
+
+std::vector<float2> twiddles_for(int n)
+{
+    switch (n) {
+    case 256: return make_twiddles<256>();
+    case 512: return make_twiddles<512>();
+    case 1024: return make_twiddles<1024>();
+    case 2048: return make_twiddles<2048>();
+    case 4096: return make_twiddles<4096>();
+    case 8192: return make_twiddles<8192>();
+    default: return {};
+    }
+}
+
+fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_EHIP; }
+
+template <int T>
+void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g)
+{
+    const int n2 = 2 * s->n;
+    const int M = int(N / n2);
+    const int streams = 2 * s->A;
+    const int colblocks = n2 / FIR_THREADS;
+    int R = 64;
+    while (R > 8 && int64_t(streams) * ((M + R - 1) / R) * colblocks < 2048)
+        R /= 2;
+    const int runs = (M + R - 1) / R;
+    const int64_t blocks = int64_t(streams) * runs * colblocks;
+    hipLaunchKernelGGL((fir_kernel<T>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
+                       raw, N * 5 / 4, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps, delays, g,
+                       n2, M, s->D, R, colblocks, runs);
+}
+
+void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g)
+{
+    switch (s->Tk) {
+    case 4: launch_fir_T<4>(s, raw, N, delays, g); break;
+    case 8: launch_fir_T<8>(s, raw, N, delays, g); break;
+    case 16: launch_fir_T<16>(s, raw, N, delays, g); break;
+    case 24: launch_fir_T<24>(s, raw, N, delays, g); break;
+    case 32: launch_fir_T<32>(s, raw, N, delays, g); break;
+    }
+}
+
+template <int N>
+void launch_post_N(const fe_stream *s, int64_t Ns, const double *delays, const double *phases,
+                   const float *gains, int8_t *out, float *y_out)
+{
+    const int M = int(Ns / (2 * N));
+    const unsigned blocks = unsigned(s->A * M);
+    if (y_out)
+        hipLaunchKernelGGL((fft_post_kernel<N, OUT_PREQUANT>), dim3(blocks), dim3(N / 8), 0, s->stream,
+                           s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, out, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->S,
+                           s->D);
+    else
+        hipLaunchKernelGGL((fft_post_kernel<N, OUT_INT8>), dim3(blocks), dim3(N / 8), 0, s->stream,
+                           s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, out, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->S,
+                           s->D);
+}
+
+void launch_post(const fe_stream *s, int64_t Ns, const double *delays, const double *phases,
+                 const float *gains, int8_t *out, float *y_out)
+{
+    switch (s->n) {
+    case 256: launch_post_N<256>(s, Ns, delays, phases, gains, out, y_out); break;
+    case 512: launch_post_N<512>(s, Ns, delays, phases, gains, out, y_out); break;
+    case 1024: launch_post_N<1024>(s, Ns, delays, phases, gains, out, y_out); break;
+    case 2048: launch_post_N<2048>(s, Ns, delays, phases, gains, out, y_out); break;
+    case 4096: launch_post_N<4096>(s, Ns, delays, phases, gains, out, y_out); break;
+    case 8192: launch_post_N<8192>(s, Ns, delays, phases, gains, out, y_out); break;
+    }
+}
+
+unsigned grid_for(int64_t work, int threads)
+{
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1)
+        b = 1;
+    if (b > 65536)
+        b = 65536;
+    return unsigned(b);
+}
+
+void launch_history_update(const fe_stream *s, const uint8_t *raw, int64_t N)
+{
+    const int streams = 2 * s->A;
+    const int64_t hb = int64_t(s->H) * 5 / 4;     // history bytes per stream
+    const int64_t nb = N * 5 / 4;                 // chunk bytes per stream
+    if (N >= s->H) {
+        hipLaunchKernelGGL(copy_rows_kernel, dim3(grid_for(hb * streams, 256)), dim3(256), 0, s->stream,
+                           s->d_hist, hb, int64_t(0), raw, nb, nb - hb, hb, streams);
+    } else {
+        // new history = old[N:] ++ chunk, assembled in the spare buffer first
+        const int64_t keep = hb - nb;
+        hipLaunchKernelGGL(copy_rows_kernel, dim3(grid_for(keep * streams, 256)), dim3(256), 0, s->stream,
+                           s->d_hist_tmp, hb, int64_t(0), s->d_hist, hb, nb, keep, streams);
+        hipLaunchKernelGGL(copy_rows_kernel, dim3(grid_for(nb * streams, 256)), dim3(256), 0, s->stream,
+                           s->d_hist_tmp, hb, keep, raw, nb, int64_t(0), nb, streams);
+        hipLaunchKernelGGL(copy_rows_kernel, dim3(grid_for(hb * streams, 256)), dim3(256), 0, s->stream,
+                           s->d_hist, hb, int64_t(0), s->d_hist_tmp, hb, int64_t(0), hb, streams);
+    }
+}
+
+fe_status check_call(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays)
+{
+    if (!s || !raw || !delays)
+        return FE_EINVAL;
+    const int64_t unit = int64_t(2) * s->n * s->S;
+    if (N <= 0 || N % unit)
+        return FE_EINVAL;
+    if (N > s->max_samples)
+        return FE_ESIZE;
+    return FE_OK;
+}
+
+fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const double *delays,
+                          const double *phases, const float *gains, int8_t *out, float *y_out,
+                          float *g_out)
+{
+    fe_status st = check_call(s, raw, N, delays);
+    if (st != FE_OK)
+        return st;
+    if (!g_out && (!phases || !gains || (!out && !y_out)))
+        return FE_EINVAL;
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess)
+        return FE_EHIP;
+    if (cur != s->device && hipSetDevice(s->device) != hipSuccess)
+        return FE_EHIP;
+    (void)hipGetLastError();
+    hipEvent_t *ev = nullptr;
+    if (s->timing && size_t(s->ev_used + 1) * 4 <= s->ev.size())
+        ev = &s->ev[size_t(s->ev_used++) * 4];
+    if (ev)
+        (void)hipEventRecord(ev[0], s->stream);
+    launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g);
+    if (ev)
+        (void)hipEventRecord(ev[1], s->stream);
+    launch_history_update(s, raw, N);
+    if (ev)
+        (void)hipEventRecord(ev[2], s->stream);
+    if (!g_out)
+        launch_post(s, N, delays, phases, gains, out, y_out);
+    if (ev)
+        (void)hipEventRecord(ev[3], s->stream);
+    st = hip_status(hipGetLastError());
+    if (cur != s->device)
+        (void)hipSetDevice(cur);
+    return st;
+}
+
+void free_events(fe_stream *s)
+{
+    for (hipEvent_t e : s->ev)
+        (void)hipEventDestroy(e);
+    s->ev.clear();
+    s->ev_used = 0;
+    s->timing = false;
+}
+
+void free_stream(fe_stream *s)
+{
+    if (!s)
+        return;
+    free_events(s);
+    (void)hipFree(s->d_taps);
+    (void)hipFree(s->d_tw);
+    (void)hipFree(s->d_untangle);
+    (void)hipFree(s->d_hist);
+    (void)hipFree(s->d_hist_tmp);
+    (void)hipFree(s->d_g);
+    (void)hipFree(s->d_status);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **out)
+{
+    if (!cfg || !out || !cfg->weights || cfg->reserved0 != 0)
+        return FE_EINVAL;
+    const int n = cfg->n_channels, T = cfg->taps;
+    if (!is_pow2(n) || n < 256 || n > 8192 || T < 1 || T > 32 || cfg->n_antennas < 1
+        || cfg->spectra_per_heap < 1 || cfg->max_delay < 0 || cfg->max_samples <= 0)
+        return FE_EINVAL;
+    const int64_t unit = int64_t(2) * n * cfg->spectra_per_heap;
+    if (cfg->max_samples % unit || cfg->max_samples > (int64_t(1) << 28))
+        return FE_EINVAL;
+    if (int64_t(cfg->max_delay) > (int64_t(1) << 24))
+        return FE_EINVAL;
+
+    fe_stream *s = new (std::nothrow) fe_stream();
+    if (!s)
+        return FE_ENOMEM;
+    s->n = n;
+    s->T = T;
+    s->Tk = kernel_taps(T);
+    s->A = cfg->n_antennas;
+    s->S = cfg->spectra_per_heap;
+    s->D = cfg->max_delay;
+    s->max_samples = cfg->max_samples;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    int64_t H = int64_t(2) * n * (s->Tk - 1) + s->D;
+    H = (H + 3) / 4 * 4;                      // whole bytes of packed samples
+    s->H = int(H);
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return FE_EHIP;
+    }
+
+    const int streams = 2 * s->A;
+    const int64_t n2 = 2 * int64_t(n);
+    const size_t taps_n = size_t(n2) * s->Tk;
+    const size_t hist_bytes = size_t(streams) * size_t(H * 5 / 4);
+    const size_t g_floats = size_t(streams) * size_t(cfg->max_samples);
+    std::vector<float2> tw = twiddles_for(n);
+    bool ok = hipMalloc(&s->d_taps, taps_n * sizeof(float)) == hipSuccess
+              && hipMalloc(&s->d_tw, tw.size() * sizeof(float2)) == hipSuccess
+              && hipMalloc(&s->d_untangle, size_t(n) * sizeof(float2)) == hipSuccess
+              && hipMalloc(&s->d_hist, hist_bytes) == hipSuccess
+              && hipMalloc(&s->d_hist_tmp, hist_bytes) == hipSuccess
+              && hipMalloc(&s->d_g, g_floats * sizeof(float)) == hipSuccess
+              && hipMalloc(&s->d_status, sizeof(int)) == hipSuccess;
+    if (!ok) {
+        free_stream(s);
+        (void)hipGetLastError();
+        return FE_ENOMEM;
+    }
+
+    std::vector<float> taps(taps_n, 0.f);
+    std::memcpy(taps.data() + size_t(n2) * (s->Tk - T), cfg->weights, size_t(n2) * T * sizeof(float));
+    std::vector<float2> unt(n);
+    for (int k = 0; k < n; ++k) {
+        const long double a = -3.141592653589793238462643383279503L * (long double)k / (long double)n;
+        unt[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+    }
+    ok = hipMemcpy(s->d_taps, taps.data(), taps_n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess
+         && hipMemcpy(s->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
+         && hipMemcpy(s->d_untangle, unt.data(), size_t(n) * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
+         && hipMemset(s->d_hist, 0, hist_bytes) == hipSuccess
+         && hipMemset(s->d_hist_tmp, 0, hist_bytes) == hipSuccess
+         && hipMemset(s->d_status, 0, sizeof(int)) == hipSuccess
+         && hipDeviceSynchronize() == hipSuccess;
+    if (!ok) {
+        free_stream(s);
+        return FE_EHIP;
+    }
+    *out = s;
+    return FE_OK;
+}
+
+fe_status fe_stream_destroy(fe_stream *s)
+{
+    if (!s)
+        return FE_OK;
+    fe_status st = hip_status(hipStreamSynchronize(s->stream));
+    free_stream(s);
+    return st;
+}
+
+fe_status fe_stream_set_hip_stream(fe_stream *s, void *hip_stream)
+{
+    if (!s)
+        return FE_EINVAL;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    return FE_OK;
+}
+
+fe_status fe_stream_reset(fe_stream *s)
+{
+    if (!s)
+        return FE_EINVAL;
+    const int64_t bytes = int64_t(2) * s->A * (int64_t(s->H) * 5 / 4);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(bytes, 256)), dim3(256), 0, s->stream,
+                       s->d_hist, bytes, s->d_status);
+    return hip_status(hipGetLastError());
+}
+
+fe_status fe_channelize(fe_stream *s, const uint8_t *raw, int64_t n_samples, const double *delays,
+                        const double *phases, const float *gains, int8_t *out)
+{
+    if (!out)
+        return FE_EINVAL;
+    return channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr);
+}
+
+fe_status fe_channelize_prequant(fe_stream *s, const uint8_t *raw, int64_t n_samples,
+                                 const double *delays, const double *phases, const float *gains,
+                                 float *y_out)
+{
+    if (!y_out)
+        return FE_EINVAL;
+    return channelize_impl(s, raw, n_samples, delays, phases, gains, nullptr, y_out, nullptr);
+}
+
+fe_status fe_channelize_fir(fe_stream *s, const uint8_t *raw, int64_t n_samples,
+                            const double *delays, float *g_out)
+{
+    if (!g_out)
+        return FE_EINVAL;
+    return channelize_impl(s, raw, n_samples, delays, nullptr, nullptr, nullptr, nullptr, g_out);
+}
+
+fe_status fe_stream_status(fe_stream *s)
+{
+    if (!s)
+        return FE_EINVAL;
+    if (hipStreamSynchronize(s->stream) != hipSuccess)
+        return FE_EHIP;
+    int v = 0;
+    if (hipMemcpy(&v, s->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+        return FE_EHIP;
+    return v ? FE_EDELAY : FE_OK;
+}
+
+fe_status fe_stream_timing(fe_stream *s, int enable)
+{
+    if (!s)
+        return FE_EINVAL;
+    if (!enable) {
+        if (hipStreamSynchronize(s->stream) != hipSuccess)
+            return FE_EHIP;
+        free_events(s);
+        return FE_OK;
+    }
+    if (s->ev.empty()) {
+        s->ev.assign(size_t(4) * 4096, nullptr);
+        for (hipEvent_t &e : s->ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                free_events(s);
+                return FE_EHIP;
+            }
+    }
+    s->ev_used = 0;
+    s->timing = true;
+    return FE_OK;
+}
+
+fe_status fe_stream_timing_read(fe_stream *s, double *fir_ms, double *post_ms, int64_t *calls)
+{
+    if (!s)
+        return FE_EINVAL;
+    double a = 0.0, b = 0.0;
+    if (s->ev_used > 0 && hipStreamSynchronize(s->stream) != hipSuccess)
+        return FE_EHIP;
+    for (int i = 0; i < s->ev_used; ++i) {
+        float x = 0.f, y = 0.f;
+        hipEvent_t *e = &s->ev[size_t(i) * 4];
+        if (hipEventElapsedTime(&x, e[0], e[1]) != hipSuccess
+            || hipEventElapsedTime(&y, e[2], e[3]) != hipSuccess)
+            return FE_EHIP;
+        a += x;
+        b += y;
+    }
+    if (fir_ms)
+        *fir_ms = a;
+    if (post_ms)
+        *post_ms = b;
+    if (calls)
+        *calls = s->ev_used;
+    s->ev_used = 0;
+    return FE_OK;
+}
+
+fe_status fe_debug_unpack10(const uint8_t *raw, int64_t first, int64_t count, int32_t *out,
+                            void *hip_stream)
+{
+    if (!raw || !out || first < 0 || count < 0)
+        return FE_EINVAL;
+    if (count == 0)
+        return FE_OK;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(count, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), raw, first, count, out);
+    return hip_status(hipGetLastError());
+}
+
+const char *fe_strerror(fe_status status)
+{
+    switch (status) {
+    case FE_OK: return "success";
+    case FE_EINVAL: return "invalid argument";
+    case FE_ENOMEM: return "device allocation failed";
+    case FE_EHIP: return "HIP runtime error";
+    case FE_EDELAY: return "coarse delay outside [0, max_delay] (spectrum zeroed)";
+    case FE_ESIZE: return "n_samples exceeds the stream's max_samples";
+    default: return "unknown status";
+    }
+}
+
+int32_t fe_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+"""ctypes binding of ``libfengine.so`` (the C ABI in ``include/fengine.h``).
+
+Argument marshalling only: every step of the channelizer runs in the HIP
+kernels of the library.  Buffers are torch tensors on the GPU; their
+``data_ptr()`` is handed to the library, which enqueues work on the HIP
+stream the :class:`Stream` was bound to.  If the library is missing this
+module raises: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+from . import build as _build
+
+FE_OK, FE_EINVAL, FE_ENOMEM, FE_EHIP, FE_EDELAY, FE_ESIZE = 0, -1, -2, -3, -4, -5
+
+
+class FEngineError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, _strerror(status), status))
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n_channels", ctypes.c_int32), ("taps", ctypes.c_int32),
+                ("n_antennas", ctypes.c_int32), ("spectra_per_heap", ctypes.c_int32),
+                ("max_delay", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("max_samples", ctypes.c_int64), ("weights", ctypes.POINTER(ctypes.c_float))]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_st = ctypes.c_int32
+
+
+def load_library(path: Optional[str] = None):
+    """Load the built library (never builds; raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or _build.LIB
+    if not os.path.exists(path):
+        raise FEngineError(FE_EINVAL, "HIP library %s is not built (run "
+                           "python -m paper_2303_09886_amd.build)" % path)
+    L = ctypes.CDLL(path)
+    L.fe_stream_create.argtypes = [ctypes.POINTER(_Config), _vp, ctypes.POINTER(_vp)]
+    L.fe_stream_create.restype = _st
+    L.fe_stream_destroy.argtypes = [_vp]
+    L.fe_stream_destroy.restype = _st
+    L.fe_stream_set_hip_stream.argtypes = [_vp, _vp]
+    L.fe_stream_set_hip_stream.restype = _st
+    L.fe_stream_reset.argtypes = [_vp]
+    L.fe_stream_reset.restype = _st
+    for name in ("fe_channelize", "fe_channelize_prequant"):
+        f = getattr(L, name)
+        f.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _vp]
+        f.restype = _st
+    L.fe_channelize_fir.argtypes = [_vp, _vp, _i64, _vp, _vp]
+    L.fe_channelize_fir.restype = _st
+    L.fe_stream_status.argtypes = [_vp]
+    L.fe_stream_status.restype = _st
+    L.fe_stream_timing.argtypes = [_vp, ctypes.c_int]
+    L.fe_stream_timing.restype = _st
+    L.fe_stream_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    L.fe_stream_timing_read.restype = _st
+    L.fe_debug_unpack10.argtypes = [_vp, _i64, _i64, _vp, _vp]
+    L.fe_debug_unpack10.restype = _st
+    L.fe_strerror.argtypes = [_st]
+    L.fe_strerror.restype = ctypes.c_char_p
+    L.fe_version.argtypes = []
+    L.fe_version.restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def _strerror(status: int) -> str:
+    try:
+        return load_library().fe_strerror(status).decode()
+    except Exception:
+        return "status"
+
+
+def _check(status: int, what: str):
+    if status != FE_OK:
+        raise FEngineError(status, what)
+
+
+def version() -> int:
+    return int(load_library().fe_version())
+
+
+def _ptr(t, dtype, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a torch tensor on the GPU" % what)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (what, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hip_stream(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Stream:
+    """One fe_stream: A antennas x 2 polarizations with state across calls.
+
+    ``weights`` is a host float32 array of 2n*T taps (copied at creation).
+    Work is enqueued on ``hip_stream`` (default: torch's current stream).
+    """
+
+    def __init__(self, n_channels: int, taps: int, n_antennas: int, weights,
+                 max_samples: int, spectra_per_heap: int = 256, max_delay: int = 128,
+                 hip_stream=None):
+        import numpy as np
+        L = load_library()
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        if w.size != 2 * n_channels * taps:
+            raise ValueError("weights must hold 2*n*T values")
+        self._w = w
+        cfg = _Config(n_channels, taps, n_antennas, spectra_per_heap, max_delay, 0, max_samples,
+                      w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        h = _vp()
+        _check(L.fe_stream_create(ctypes.byref(cfg), _hip_stream(hip_stream), ctypes.byref(h)),
+               "fe_stream_create")
+        self._h = h
+        self.n, self.taps, self.A = n_channels, taps, n_antennas
+        self.S, self.max_delay, self.max_samples = spectra_per_heap, max_delay, max_samples
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load_library().fe_stream_destroy(self._h), "fe_stream_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- calls ------------------------------------------------------------
+    def set_hip_stream(self, stream):
+        _check(load_library().fe_stream_set_hip_stream(self._h, _hip_stream(stream)),
+               "fe_stream_set_hip_stream")
+
+    def reset(self):
+        _check(load_library().fe_stream_reset(self._h), "fe_stream_reset")
+
+    def status(self) -> int:
+        """Synchronize and return the sticky status (FE_OK or FE_EDELAY)."""
+        st = int(load_library().fe_stream_status(self._h))
+        if st not in (FE_OK, FE_EDELAY):
+            raise FEngineError(st, "fe_stream_status")
+        return st
+
+    def timing(self, enable: bool):
+        """Record HIP events around this stream's kernels on every call."""
+        _check(load_library().fe_stream_timing(self._h, 1 if enable else 0), "fe_stream_timing")
+
+    def timing_read(self):
+        """(fir_ms, post_ms, calls) summed since the last read; synchronizes."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), _i64()
+        _check(load_library().fe_stream_timing_read(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                    ctypes.byref(c)), "fe_stream_timing_read")
+        return a.value, b.value, int(c.value)
+
+    def _args(self, raw, n_samples, delays, phases=None, gains=None):
+        import torch
+        out = [self._h, _ptr(raw, torch.uint8, "raw"), int(n_samples),
+               _ptr(delays, torch.float64, "delays")]
+        if phases is not None:
+            out.append(_ptr(phases, torch.float64, "phases"))
+        if gains is not None:
+            out.append(_ptr(gains, torch.float32, "gains"))
+        return out
+
+    def channelize(self, raw, n_samples: int, delays, phases, gains, out):
+        """Enqueue fe_channelize; ``out`` int8 [A][M/S_h][n][S_h][2][2]."""
+        import torch
+        a = self._args(raw, n_samples, delays, phases, gains) + [_ptr(out, torch.int8, "out")]
+        _check(load_library().fe_channelize(*a), "fe_channelize")
+
+    def channelize_prequant(self, raw, n_samples: int, delays, phases, gains, y_out):
+        """Enqueue fe_channelize_prequant; ``y_out`` float32 [A][2][M][n][2]."""
+        import torch
+        a = self._args(raw, n_samples, delays, phases, gains) + [_ptr(y_out, torch.float32, "y_out")]
+        _check(load_library().fe_channelize_prequant(*a), "fe_channelize_prequant")
+
+    def channelize_fir(self, raw, n_samples: int, delays, g_out):
+        """Enqueue fe_channelize_fir; ``g_out`` float32 [A][2][M][2n]."""
+        import torch
+        a = self._args(raw, n_samples, delays) + [_ptr(g_out, torch.float32, "g_out")]
+        _check(load_library().fe_channelize_fir(*a), "fe_channelize_fir")
+
+
+def debug_unpack10(raw, first: int, count: int, out, hip_stream=None):
+    """Enqueue fe_debug_unpack10 (int32 ``out`` of ``count`` samples)."""
+    import torch
+    _check(load_library().fe_debug_unpack10(_ptr(raw, torch.uint8, "raw"), int(first), int(count),
+                                            _ptr(out, torch.int32, "out"), _hip_stream(hip_stream)),
+           "fe_debug_unpack10")

@@ -1,0 +1,302 @@
+"""Parity of the HIP channelizer with the FP64 oracle (needs an MI355X).
+
+All calls go through the C ABI (ctypes binding).  Inputs are seeded and
+synthetic (synth).  Tolerances (oracle.compare): unpack and coarse delay
+bit-exact; pre-quantisation spectra within 1e-5 relative; int8 exact except
+within 1e-3 of a rounding boundary, where +-1 is allowed.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import compare
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2303_09886_amd as fe   # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make_stream(w, max_samples, max_delay=128):
+    s = w.shape
+    return fe.Stream(s.n, s.taps, s.antennas, w.weights, max_samples,
+                     spectra_per_heap=s.spectra_per_heap, max_delay=max_delay)
+
+
+def gpu_run(w, chunk, mode="int8", max_delay=128, stream=None):
+    """Feed the workload to a fresh stream in calls of ``chunk`` samples;
+    return the concatenated output of the requested kind."""
+    s = w.shape
+    A, n, S = s.antennas, s.n, s.spectra_per_heap
+    st = stream or make_stream(w, chunk, max_delay)
+    gains = dev(w.gains)
+    outs = []
+    for start in range(0, w.total, chunk):
+        raw, d, p = w.chunk(start, chunk)
+        M = chunk // (2 * n)
+        raw_t, d_t, p_t = dev(raw), dev(d), dev(p)
+        if mode == "int8":
+            o = torch.empty((A, M // S, n, S, 2, 2), dtype=torch.int8, device="cuda")
+            st.channelize(raw_t, chunk, d_t, p_t, gains, o)
+        elif mode == "prequant":
+            o = torch.empty((A, 2, M, n, 2), dtype=torch.float32, device="cuda")
+            st.channelize_prequant(raw_t, chunk, d_t, p_t, gains, o)
+        else:
+            o = torch.empty((A, 2, M, 2 * n), dtype=torch.float32, device="cuda")
+            st.channelize_fir(raw_t, chunk, d_t, o)
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy())
+    status = st.status()
+    if stream is None:
+        st.close()
+    axis = 1 if mode == "int8" else 2
+    out = np.concatenate(outs, axis=axis)
+    if mode == "prequant":
+        out = out[..., 0] + 1j * out[..., 1]
+    return out, status
+
+
+def oracle_run(w, want=("y", "q"), max_delay=128):
+    s = w.shape
+    return oracle.channelize(w.raw, w.total, s.n, s.taps, max_delay, w.weights, w.delays,
+                             w.phases, w.gains, want=want)
+
+
+def check_int8(q_gpu, ref, S, context=""):
+    q_ref = oracle.heap_layout(ref["q"], S)
+    v_ref = compare.heap_values(ref["y"], S)
+    hard, soft = compare.int8_mismatches(q_gpu, q_ref, v_ref)
+    _say("int8 %s: %d hard mismatches, %d boundary differences of %d values"
+         % (context, hard, soft, q_ref.size))
+    assert hard == 0
+    return soft
+
+
+# --------------------------------------------------------------------------
+# Step 1 alone: the device unpacker is bit-exact
+# --------------------------------------------------------------------------
+
+def test_unpack_bit_exact():
+    rng = np.random.default_rng(7)
+    raw = rng.integers(0, 256, size=(1 << 17) * 5, dtype=np.uint8)
+    count = raw.size * 8 // 10
+    out = torch.empty(count, dtype=torch.int32, device="cuda")
+    fe.debug_unpack10(dev(raw), 0, count, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.unpack10(raw, 0, count))
+    for first in (1, 2, 3, 5, 1001):
+        o = torch.empty(777, dtype=torch.int32, device="cuda")
+        fe.debug_unpack10(dev(raw), first, 777, o)
+        torch.cuda.synchronize()
+        assert np.array_equal(o.cpu().numpy(), oracle.unpack10(raw, first, 777))
+    codes = np.arange(-512, 512)
+    for lead in range(4):
+        x = np.concatenate([np.zeros(lead, dtype=np.int64), codes, np.zeros(4 - lead, dtype=np.int64)])
+        packed = synth.pack10(x)
+        o = torch.empty(x.size, dtype=torch.int32, device="cuda")
+        fe.debug_unpack10(dev(packed), 0, x.size, o)
+        torch.cuda.synchronize()
+        assert np.array_equal(o.cpu().numpy(), x)
+
+
+# --------------------------------------------------------------------------
+# Steps 1-3a: FIR output with impulses is exact; with noise within 1e-5
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,T", [(1024, 16), (256, 4), (4096, 16), (512, 24), (2048, 3)])
+def test_fir_impulses_bit_exact(n, T):
+    """One impulse per window: g must equal float32(value * h[u]) exactly,
+    which pins the sample order, the coarse-delay index and the tap mapping."""
+    _say("fir impulses n=%d T=%d" % (n, T))
+    S, A = 4, 2
+    M = 8 * S
+    shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 99)
+    x = np.zeros_like(w.x)
+    rng = np.random.default_rng(n + T)
+    spacing = 2 * n * (T + 2)
+    for a in range(A):
+        for p in range(2):
+            pos = np.arange(rng.integers(0, 2 * n), w.total, spacing)
+            x[a, p, pos] = rng.choice([-512, 511, 1, -1, 300], size=pos.size)
+    w.x, w.raw = x, synth.pack10(x)
+    w.delays[:] = np.floor(rng.uniform(0, 100, size=(A, 2, 1))) + np.floor(
+        np.arange(M) / 5)[None, None, :]                     # integer delays, stepping
+    g, status = gpu_run(w, w.total, mode="fir")
+    assert status == fe.FE_OK
+    ref = oracle_run(w, want=("g",))
+    assert np.array_equal(g, ref["g"].astype(np.float32))
+
+
+@pytest.mark.parametrize("n,T,A,S,M", [(1024, 16, 1, 4, 44), (4096, 16, 2, 4, 36), (256, 8, 3, 2, 70)])
+def test_fir_matches_oracle(n, T, A, S, M):
+    _say("fir noise n=%d T=%d A=%d M=%d" % (n, T, A, M))
+    shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 5)
+    g, _ = gpu_run(w, w.total, mode="fir")
+    ref = oracle_run(w, want=("g",))
+    nw, el = compare.prequant_errors(g, ref["g"])
+    _say("  g normwise %.3g elementwise %.3g" % (nw, el))
+    assert nw <= 1e-5 and el <= 1e-5
+
+
+# --------------------------------------------------------------------------
+# Whole path against the oracle
+# --------------------------------------------------------------------------
+
+CASES = [
+    # n, T, A, S_h, M (spectra per call), calls
+    (1024, 16, 1, 4, 44, 1),
+    (4096, 16, 2, 4, 36, 1),
+    (256, 4, 3, 8, 64, 2),
+    (512, 24, 1, 2, 30, 2),
+    (2048, 32, 1, 4, 40, 1),
+    (8192, 8, 1, 2, 18, 1),
+    (1024, 13, 2, 8, 48, 3),
+    (1024, 1, 1, 4, 20, 1),
+]
+
+
+@pytest.mark.parametrize("n,T,A,S,M,calls", CASES)
+def test_prequant_matches_oracle(n, T, A, S, M, calls):
+    _say("prequant n=%d T=%d A=%d S=%d M=%d calls=%d" % (n, T, A, S, M, calls))
+    shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 1000 + n + T, total=2 * n * M * calls)
+    y, status = gpu_run(w, 2 * n * M, mode="prequant")
+    assert status == fe.FE_OK
+    ref = oracle_run(w, want=("y",))
+    nw, el = compare.assert_prequant_close(y, ref["y"])
+    _say("  Y normwise %.3g elementwise %.3g" % (nw, el))
+
+
+@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4])
+def test_int8_matches_oracle(n, T, A, S, M, calls):
+    _say("int8 n=%d T=%d A=%d S=%d M=%d calls=%d" % (n, T, A, S, M, calls))
+    shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 2000 + n + T, total=2 * n * M * calls)
+    q, status = gpu_run(w, 2 * n * M, mode="int8")
+    assert status == fe.FE_OK
+    ref = oracle_run(w)
+    check_int8(q, ref, S, "n=%d" % n)
+
+
+def test_calls_shorter_than_history():
+    """N < H: the history is shifted rather than replaced."""
+    n, T, S = 256, 16, 2
+    shape = synth.Shape(n=n, taps=T, antennas=2, samples=2 * n * S, spectra_per_heap=S)
+    w = synth.make_workload(shape, 77, total=2 * n * S * 20)
+    q, status = gpu_run(w, 2 * n * S, mode="int8")
+    assert status == fe.FE_OK
+    ref = oracle_run(w)
+    check_int8(q, ref, S, "short calls")
+    y, _ = gpu_run(w, 2 * n * S, mode="prequant")
+    compare.assert_prequant_close(y, ref["y"])
+
+
+def test_chunking_is_invisible_and_deterministic():
+    """One call of 4N equals four calls of N bit for bit; reruns are identical."""
+    n, T, S = 1024, 16, 4
+    shape = synth.Shape(n=n, taps=T, antennas=2, samples=2 * n * S * 4, spectra_per_heap=S)
+    w = synth.make_workload(shape, 3)
+    q1, _ = gpu_run(w, w.total)
+    q4, _ = gpu_run(w, w.total // 4)
+    q1b, _ = gpu_run(w, w.total)
+    assert np.array_equal(q1, q4)
+    assert np.array_equal(q1, q1b)
+
+
+def test_out_of_range_delay_sets_status_and_zeroes():
+    n, T, S, M = 1024, 16, 4, 16
+    shape = synth.Shape(n=n, taps=T, antennas=1, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 4)
+    w.delays[0, 1, 5] = 128.7          # c = 129 > max_delay
+    w.delays[0, 0, 9] = np.nan
+    w.delays[0, 0, 11] = -3.0
+    y, status = gpu_run(w, w.total, mode="prequant")
+    assert status == fe.FE_EDELAY
+    ref = oracle_run(w, want=("y", "valid"))
+    assert ref["invalid"] == 3
+    assert not y[0, 1, 5].any() and not y[0, 0, 9].any() and not y[0, 0, 11].any()
+    compare.assert_prequant_close(y, ref["y"])
+    # reset clears the sticky status
+    st = make_stream(w, w.total)
+    raw, d, p = w.chunk(0, w.total)
+    o = torch.empty((1, 2, M, n, 2), dtype=torch.float32, device="cuda")
+    st.channelize_prequant(dev(raw), w.total, dev(d), dev(p), dev(w.gains), o)
+    assert st.status() == fe.FE_EDELAY
+    st.reset()
+    assert st.status() == fe.FE_OK
+    st.close()
+
+
+def test_host_validation_with_live_stream():
+    n, T, S, M = 1024, 16, 4, 8
+    shape = synth.Shape(n=n, taps=T, antennas=1, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 4)
+    st = make_stream(w, w.total)
+    raw, d, p = w.chunk(0, w.total)
+    o = torch.empty((1, M // S, n, S, 2, 2), dtype=torch.int8, device="cuda")
+    with pytest.raises(fe.FEngineError) as e:
+        st.channelize(dev(raw), w.total // 2 + 2 * n, dev(d), dev(p), dev(w.gains), o)
+    assert e.value.status == fe.FE_EINVAL
+    with pytest.raises(fe.FEngineError) as e:
+        st.channelize(dev(raw), 2 * w.total, dev(d), dev(p), dev(w.gains), o)
+    assert e.value.status == fe.FE_ESIZE
+    st.close()
+
+
+# --------------------------------------------------------------------------
+# Full-size configurations, in the launch configuration the benchmark times
+# --------------------------------------------------------------------------
+
+def test_small_config_full():
+    """1 antenna x 2 pols, 2^20 samples/pol, 1024 channels, 16 taps: every output."""
+    _say("small config, full comparison")
+    w = synth.make_workload(synth.SMALL, 1)
+    q, status = gpu_run(w, w.total, mode="int8")
+    assert status == fe.FE_OK
+    ref = oracle_run(w)
+    check_int8(q, ref, synth.SMALL.spectra_per_heap, "small config")
+    y, _ = gpu_run(w, w.total, mode="prequant")
+    nw, el = compare.assert_prequant_close(y, ref["y"])
+    _say("  Y normwise %.3g elementwise %.3g" % (nw, el))
+
+
+def test_large_config_sampled():
+    """4 antennas x 2 pols, 2^24 samples/pol, 4096 channels, 16 taps; the
+    oracle checks sampled spectra (stream start, heap edges, the end)."""
+    _say("large config, sampled comparison")
+    w = synth.make_workload(synth.LARGE, 2)
+    shape = w.shape
+    q, status = gpu_run(w, w.total, mode="int8")
+    assert status == fe.FE_OK
+    S, n = shape.spectra_per_heap, shape.n
+    for F in (0, 1, 14, 15, 16, 255, 256, 1000, 1023, 1024, 2047):
+        ref = oracle.channelize(w.raw, w.total, n, shape.taps, 128, w.weights, w.delays,
+                                w.phases, w.gains, F, F + 1, want=("y", "q"))
+        got = q[:, F // S, :, F % S]                       # [A][n][2][2]
+        q_ref = ref["q"][:, :, 0].transpose(0, 2, 1, 3)    # [A][n][2][2]
+        v = ref["y"][:, :, 0].transpose(0, 2, 1)
+        v_ref = np.stack([v.real, v.imag], -1)
+        hard, soft = compare.int8_mismatches(got, q_ref, v_ref)
+        assert hard == 0, F
+    y, _ = gpu_run(w, w.total, mode="prequant")
+    for F in (0, 15, 16, 1024, 2047):
+        ref = oracle.channelize(w.raw, w.total, n, shape.taps, 128, w.weights, w.delays,
+                                w.phases, w.gains, F, F + 1, want=("y",))
+        compare.assert_prequant_close(y[:, :, F:F + 1], ref["y"])
