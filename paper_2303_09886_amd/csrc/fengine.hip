@@ -96,18 +96,50 @@ __device__ __forceinline__ bool split_delay(double d, int D, int &c, double &tau
     return true;
 }
 
+// Wavefront dispatch sends workgroup b to XCD b mod 8.  Map it to a logical
+// index so that each XCD works on one contiguous range of logical indices:
+// neighbouring tiles then share an L2 (which merges their partial writes to
+// the same lines and serves the input bytes they share).
+__device__ __forceinline__ int xcd_logical(int b, int G)
+{
+    constexpr int X = 8;
+    const int xcd = b % X, local = b / X;
+    const int per = (G + X - 1) / X;
+    int full = G % X;
+    if (full == 0)
+        full = X;
+    return xcd < full ? xcd * per + local : full * per + (xcd - full) * (per - 1) + local;
+}
+
 // ---------------------------------------------------------------------------
 // Kernel 1: unpack + coarse delay + FIR (Eq. (1)).
 //
 // Thread = one column t of one stream (antenna, pol) for a run of R <= 64
 // consecutive spectra.  g_{F,t} = sum_j s[2n(F-T+1) - c_F + t + 2nj] h[t+2nj].
-// For consecutive spectra with the same c the window rows shift by one, so
-// one new sample is unpacked per spectrum; a change of c reloads the window.
-// The delay split of spectrum m0+l is computed by lane l and broadcast with
-// readlane (wave-uniform), so c is an SGPR in the hot loop.
+// Viewed down column t, spectrum F reads rows F-T+1 .. F of the 2n-wide
+// sample matrix shifted by c_F, so consecutive spectra with equal c share
+// T-1 rows and each new spectrum needs one new sample.  Spectra go in groups
+// of T: the group's T new samples are loaded together (memory-level
+// parallelism), then its T outputs are formed from a 2T-1 register window.
+// Groups whose spectra all have the previous delay and read no history take
+// this fast path; anything else (a delay step, the history seam, the ragged
+// tail, an invalid delay) takes a general per-spectrum path.  The delay
+// split of spectrum m0+l is computed by lane l and broadcast with readlane,
+// so c is wave-uniform (SGPR) in the loop.
 // ---------------------------------------------------------------------------
 
 constexpr int FIR_THREADS = 256;
+
+// 10-bit field from the two bytes at p[0], p[1] (big-endian bit order),
+// starting `sh` bits below the MSB of p[0].
+__device__ __forceinline__ float field10(const uint8_t *__restrict__ p, uint32_t lo_shift)
+{
+    uint16_t u;
+    __builtin_memcpy(&u, p, 2);                               // little-endian load
+    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, uint32_t(u), 0x0C0C0001u));   // byte swap
+    const int32_t x = __builtin_amdgcn_sbfe(be, lo_shift, 10u);   // sign-extending extract
+    return float(x);
+}
 
 template <int T>
 __global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
@@ -116,12 +148,13 @@ __global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
     const float *__restrict__ taps, const double *__restrict__ delays,
     float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs)
 {
-    const int b = blockIdx.x;
-    const int cb = b % colblocks;
-    const int rest = b / colblocks;
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int cb = lb % colblocks;
+    const int rest = lb / colblocks;
     const int run = rest % runs;
     const int s = rest / runs;
     const int t = cb * FIR_THREADS + threadIdx.x;
+    const int t_wave = __builtin_amdgcn_readfirstlane(cb * FIR_THREADS + (threadIdx.x & ~63));
     const int m0 = run * R;
     const int mend = min(m0 + R, M);
 
@@ -140,37 +173,70 @@ __global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
     const uint8_t *rs = raw + int64_t(s) * raw_stride;
     const uint8_t *hs = hist + int64_t(s) * hist_stride;
     float *gs = g + int64_t(s) * M * n2 + t;
+    const int row_bytes = (n2 / 4) * 5;                       // 2n samples of 10 bits
 
-    float w[T];
+    // X[i] holds the sample of row (g0 - T + 1 + i) at the current delay
+    float X[2 * T - 1];
 #pragma unroll
-    for (int j = 0; j < T; ++j)
-        w[j] = 0.f;
-    int c_prev = -1;
+    for (int i = 0; i < 2 * T - 1; ++i)
+        X[i] = 0.f;
+    int c_cur = -1;                                           // delay the window rows belong to
 
-    for (int m = m0; m < mend; m += T) {
+    for (int g0 = m0; g0 < mend; g0 += T) {
+        bool fast = g0 + T <= mend && c_cur >= 0;
+        if (fast) {
 #pragma unroll
-        for (int r = 0; r < T; ++r) {
-            const int mm = m + r;
-            if (mm < mend) {
-                const int c = __builtin_amdgcn_readlane(c_lane, mm - m0);
-                const int ok = __builtin_amdgcn_readlane(ok_lane, mm - m0);
-                // index of window row j = 0, relative to this call's first sample
-                const int64_t base = int64_t(n2) * (mm - T + 1) - c + t;
-                if (c != c_prev) {
+            for (int r = 0; r < T; ++r)
+                fast = fast && __builtin_amdgcn_readlane(c_lane, g0 - m0 + r) == c_cur;
+            // the group's new samples all lie in this call's chunk
+            fast = fast && int64_t(n2) * g0 - c_cur + t_wave >= 0;
+        }
+        if (fast) {
+            // rows g0 .. g0+T-1 of column t at delay c_cur
+            const int64_t i0 = int64_t(n2) * g0 - c_cur + t;
+            const uint32_t sh = 6u - ((uint32_t(i0) & 3u) << 1);
+            const uint8_t *p = rs + ((5 * i0) >> 2);
 #pragma unroll
-                    for (int j = 0; j < T; ++j)
-                        w[(r + j) % T] = float(sample_at(rs, hs, base + int64_t(n2) * j, H));
-                    c_prev = c;
-                } else {
-                    w[(r + T - 1) % T] = float(sample_at(rs, hs, base + int64_t(n2) * (T - 1), H));
-                }
+            for (int r = 0; r < T; ++r)
+                X[T - 1 + r] = field10(p + int64_t(r) * row_bytes, sh);
+#pragma unroll
+            for (int r = 0; r < T; ++r) {
                 float acc = 0.f;
 #pragma unroll
                 for (int j = 0; j < T; ++j)
-                    acc = fmaf(w[(r + j) % T], h[j], acc);
-                gs[int64_t(mm) * n2] = ok ? acc : 0.f;
+                    acc = fmaf(X[r + j], h[j], acc);
+                const int ok = __builtin_amdgcn_readlane(ok_lane, g0 - m0 + r);
+                gs[int64_t(g0 + r) * n2] = ok ? acc : 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < T; ++r) {
+                const int m = g0 + r;
+                if (m < mend) {
+                    const int c = __builtin_amdgcn_readlane(c_lane, m - m0);
+                    // index of window row j = 0 (row m-T+1), relative to this call's first sample
+                    const int64_t base = int64_t(n2) * (m - T + 1) - c + t;
+                    if (c != c_cur) {
+#pragma unroll
+                        for (int j = 0; j < T; ++j)
+                            X[r + j] = float(sample_at(rs, hs, base + int64_t(n2) * j, H));
+                        c_cur = c;
+                    } else {
+                        X[r + T - 1] = float(sample_at(rs, hs, base + int64_t(n2) * (T - 1), H));
+                    }
+                    float acc = 0.f;
+#pragma unroll
+                    for (int j = 0; j < T; ++j)
+                        acc = fmaf(X[r + j], h[j], acc);
+                    const int ok = __builtin_amdgcn_readlane(ok_lane, m - m0);
+                    gs[int64_t(m) * n2] = ok ? acc : 0.f;
+                }
             }
         }
+        // rows g0+1 .. g0+T-1 become the first T-1 rows of the next group
+#pragma unroll
+        for (int i = 0; i < T - 1; ++i)
+            X[i] = X[i + T];
     }
 }
 
@@ -296,6 +362,12 @@ __host__ __device__ constexpr int tw_L(int p)
     return L;
 }
 
+// LDS layout of one polarization's n points: one float2 of padding after
+// every 16, so that the radix-16 pass with L = 1 (lane stride 16 elements)
+// and the L = 16 pass (groups of 16 at stride 256) hit distinct banks.
+constexpr int lds_pad(int i) { return i + (i >> 4); }
+template <int N> constexpr int lds_len() { return N + N / 16; }
+
 // One Stockham pass (radix R, L = product of earlier radices) over one
 // polarization's n points held in LDS (or, for the first pass, read straight
 // from the float32 g of this spectrum: z[m] = g[2m] + i g[2m+1]).
@@ -314,7 +386,7 @@ __device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, const float2 
         const int b = tp + u * NTP;
 #pragma unroll
         for (int q = 0; q < R; ++q)
-            v[u][q] = FIRST ? src[b + q * NB] : buf[b + q * NB];
+            v[u][q] = FIRST ? src[b + q * NB] : buf[lds_pad(b + q * NB)];
     }
     if (!FIRST)
         __syncthreads();
@@ -331,7 +403,7 @@ __device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, const float2 
         const int base = (b - j) * R + j;
 #pragma unroll
         for (int r = 0; r < R; ++r)
-            buf[base + r * L] = v[u][r];
+            buf[lds_pad(base + r * L)] = v[u][r];
     }
     __syncthreads();
 }
@@ -347,20 +419,6 @@ __device__ __forceinline__ void fft_run(float2 *buf, const float2 *src, int tp, 
     }
 }
 
-// Wavefront dispatch sends workgroup b to XCD b mod 8.  Map it to a logical
-// index so that each XCD works on one contiguous range of logical indices:
-// consecutive spectra of an antenna then share an L2, which merges their
-// partial writes into the same output lines.
-__device__ __forceinline__ int xcd_logical(int b, int G)
-{
-    constexpr int X = 8;
-    const int xcd = b % X, local = b / X;
-    const int per = (G + X - 1) / X;
-    int full = G % X;
-    if (full == 0)
-        full = X;
-    return xcd < full ? xcd * per + local : full * per + (xcd - full) * (per - 1) + local;
-}
 
 // ---------------------------------------------------------------------------
 // Kernel 2: FFT + R2C untangle + fine delay/phase + gain + quantise + store.
@@ -381,7 +439,8 @@ __global__ __launch_bounds__(N / 8) void fft_post_kernel(
     constexpr int NT = N / 8;
     constexpr int NTP = N / 16;
     constexpr int NH = N / 64;             // coarse phase-table entries (k >> 6)
-    __shared__ float2 buf[2 * N];
+    constexpr int NP = lds_len<N>();
+    __shared__ float2 buf[2 * NP];
     __shared__ float2 ph_hi[2][NH < 1 ? 1 : NH];
     __shared__ float2 ph_lo[2][64];
 
@@ -427,7 +486,7 @@ __global__ __launch_bounds__(N / 8) void fft_post_kernel(
 
     // forward n-point complex FFT of z[m] = g[2m] + i g[2m+1] per polarization
     const float2 *src = reinterpret_cast<const float2 *>(g + ((int64_t(a) * 2 + pol) * M + F) * (2 * N));
-    fft_run<N, 0>(buf + pol * N, src, tp, tw_all);
+    fft_run<N, 0>(buf + pol * NP, src, tp, tw_all);
 
     // post-processing: thread owns channels k = tid + NT i for both pols
     const float2 *gain0 = gains + (int64_t(a) * 2 + 0) * N;
@@ -440,8 +499,8 @@ __global__ __launch_bounds__(N / 8) void fft_post_kernel(
         float2 Y[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            const float2 zk = buf[p * N + k];
-            const float2 zm = buf[p * N + km];
+            const float2 zk = buf[p * NP + lds_pad(k)];
+            const float2 zm = buf[p * NP + lds_pad(km)];
             // E = (Z[k] + conj Z[n-k]) / 2, O = (Z[k] - conj Z[n-k]) / (2i)
             const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
             const float2 O = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
@@ -587,8 +646,9 @@ void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const doubl
     const int M = int(N / n2);
     const int streams = 2 * s->A;
     const int colblocks = n2 / FIR_THREADS;
+    // runs of R spectra; R >= 2T keeps whole groups of T for the fast path
     int R = 64;
-    while (R > 8 && int64_t(streams) * ((M + R - 1) / R) * colblocks < 2048)
+    while (R > 2 * T && int64_t(streams) * ((M + R - 1) / R) * colblocks < 1024)
         R /= 2;
     const int runs = (M + R - 1) / R;
     const int64_t blocks = int64_t(streams) * runs * colblocks;

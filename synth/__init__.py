@@ -23,7 +23,8 @@ public dataset):
   1024), the other two at U(0.01, 0.49) cycles/sample, A_q ~ U(10, 100),
   psi_q ~ U(0, 2*pi);
 * delays   d_F = d0 + r * 2n * F (+ a small per-polarization offset),
-  d0 ~ U(5, 95), rate r given per workload;
+  d0 ~ U(5, 95), r ~ U(-r_max, r_max) with r_max the workload's rate capped so
+  that d stays within [1, 127] over the whole stream;
 * phases   phi_F = phi0 + w * 2n * F, phi0 ~ U(0, 2*pi), w ~ U(-1e-4, 1e-4);
 * gains    |G| ~ U(0.5, 2), arg G ~ U(0, 2*pi), per (antenna, pol, channel);
 * taps     Hann-windowed sinc (Sec. 5.2), see :func:`pfb_taps`.
@@ -182,9 +183,9 @@ def make_workload(shape: Shape, seed: int, total: Optional[int] = None, *,
                   antennas: Optional[int] = None) -> Workload:
     """Build the seeded inputs of ``shape`` for ``total`` samples per pol.
 
-    ``delay_rate`` is the delay slope in samples per sample; the default
-    (1e-5) is far above the paper's sidereal rate (< 3e-9, Sec. 3.3) so that
-    the integer part of the delay steps inside one call.
+    ``delay_rate`` is the largest delay slope in samples per sample; the
+    default (1e-5) is far above the paper's sidereal rate (< 3e-9, Sec. 3.3)
+    so that the integer part of the delay steps inside one call.
     """
     n, A = shape.n, (shape.antennas if antennas is None else antennas)
     total = shape.samples if total is None else total
@@ -212,9 +213,12 @@ def make_workload(shape: Shape, seed: int, total: Optional[int] = None, *,
     rd = np.random.default_rng(kids[A])
     F = np.arange(M, dtype=np.float64)
     delays = np.empty((A, 2, M), dtype=np.float64)
+    span = 2.0 * n * max(M - 1, 1)
     for a in range(A):
         d0 = rd.uniform(5, 95)
-        rate = rd.uniform(-delay_rate, delay_rate)
+        # the slope is capped so that d stays in [1, 127] over the stream
+        r_max = min(delay_rate, (d0 - 1.0) / span, (127.0 - d0) / span)
+        rate = rd.uniform(-r_max, r_max)
         off = rd.uniform(-pol_delay_offset, pol_delay_offset)
         delays[a, 0] = d0 + rate * 2 * n * F
         delays[a, 1] = d0 + off + rate * 2 * n * F

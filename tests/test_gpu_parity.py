@@ -118,13 +118,15 @@ def test_unpack_bit_exact():
 # Steps 1-3a: FIR output with impulses is exact; with noise within 1e-5
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,T", [(1024, 16), (256, 4), (4096, 16), (512, 24), (2048, 3)])
-def test_fir_impulses_bit_exact(n, T):
+@pytest.mark.parametrize("n,T,step", [(1024, 16, 5), (256, 4, 5), (4096, 16, 5), (512, 24, 5),
+                                      (2048, 3, 5), (1024, 16, 0), (256, 32, 0), (512, 8, 40)])
+def test_fir_impulses_bit_exact(n, T, step):
     """One impulse per window: g must equal float32(value * h[u]) exactly,
-    which pins the sample order, the coarse-delay index and the tap mapping."""
-    _say("fir impulses n=%d T=%d" % (n, T))
+    which pins the sample order, the coarse-delay index and the tap mapping.
+    step = spectra between integer-delay steps (0: constant delay)."""
+    _say("fir impulses n=%d T=%d step=%d" % (n, T, step))
     S, A = 4, 2
-    M = 8 * S
+    M = 32 * S if step != 5 else 8 * S
     shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
     w = synth.make_workload(shape, 99)
     x = np.zeros_like(w.x)
@@ -135,8 +137,8 @@ def test_fir_impulses_bit_exact(n, T):
             pos = np.arange(rng.integers(0, 2 * n), w.total, spacing)
             x[a, p, pos] = rng.choice([-512, 511, 1, -1, 300], size=pos.size)
     w.x, w.raw = x, synth.pack10(x)
-    w.delays[:] = np.floor(rng.uniform(0, 100, size=(A, 2, 1))) + np.floor(
-        np.arange(M) / 5)[None, None, :]                     # integer delays, stepping
+    ramp = np.floor(np.arange(M) / step) if step else np.zeros(M)
+    w.delays[:] = np.floor(rng.uniform(0, 100, size=(A, 2, 1))) + ramp[None, None, :]
     g, status = gpu_run(w, w.total, mode="fir")
     assert status == fe.FE_OK
     ref = oracle_run(w, want=("g",))
@@ -169,6 +171,12 @@ CASES = [
     (8192, 8, 1, 2, 18, 1),
     (1024, 13, 2, 8, 48, 3),
     (1024, 1, 1, 4, 20, 1),
+    # long runs of constant delay: the FIR's grouped fast path, T = 4 .. 32
+    (256, 4, 1, 32, 256, 1),
+    (256, 8, 2, 32, 192, 2),
+    (512, 16, 1, 64, 256, 1),
+    (256, 24, 1, 32, 256, 1),
+    (256, 32, 1, 64, 256, 1),
 ]
 
 
@@ -184,7 +192,7 @@ def test_prequant_matches_oracle(n, T, A, S, M, calls):
     _say("  Y normwise %.3g elementwise %.3g" % (nw, el))
 
 
-@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4])
+@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10])
 def test_int8_matches_oracle(n, T, A, S, M, calls):
     _say("int8 n=%d T=%d A=%d S=%d M=%d calls=%d" % (n, T, A, S, M, calls))
     shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
