@@ -130,23 +130,48 @@ __device__ __forceinline__ int xcd_logical(int b, int G)
 
 constexpr int FIR_THREADS = 256;
 
-// 10-bit field from the two bytes at p[0], p[1] (big-endian bit order),
-// starting `sh` bits below the MSB of p[0].
-__device__ __forceinline__ float field10(const uint8_t *__restrict__ p, uint32_t lo_shift)
+// Raw buffer descriptor (gfx9 family): base, no stride, `bytes` records;
+// loads outside [0, bytes) return zero, stores outside are dropped.  Used for
+// aligned 32-bit stores only (16-bit buffer loads at odd byte addresses do
+// not behave like unaligned global loads).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes), 0x00020000);
+}
+
+// Store one float through a buffer descriptor (the builtin's payload is a
+// 32-bit integer: pass the bits, not a converted value).
+__device__ __forceinline__ void store_f32(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+}
+
+// Unaligned 16-bit global load (little-endian) at byte `off` of a
+// wave-uniform base (so the address is an SGPR pair plus one 32-bit VGPR).
+__device__ __forceinline__ uint32_t load_u16(const uint8_t *base, uint32_t off)
 {
     uint16_t u;
-    __builtin_memcpy(&u, p, 2);                               // little-endian load
-    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, uint32_t(u), 0x0C0C0001u));   // byte swap
-    const int32_t x = __builtin_amdgcn_sbfe(be, lo_shift, 10u);   // sign-extending extract
+    __builtin_memcpy(&u, base + off, 2);
+    return u;
+}
+
+// 10-bit sample from a little-endian 16-bit load u of the bytes holding it;
+// its MSB sits `lo_shift` + 9 bits up in the big-endian (byte-swapped) word.
+__device__ __forceinline__ float field10(uint32_t u, uint32_t lo_shift)
+{
+    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, u, 0x0C0C0001u));   // byte swap
+    // sign-extending extract; the builtin's result type is unsigned, so cast
+    // back to int before converting (else the conversion is unsigned)
+    const int32_t x = int32_t(__builtin_amdgcn_sbfe(be, lo_shift, 10u));
     return float(x);
 }
 
 template <int T>
-__global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
+__global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
-    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs)
+    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me)
 {
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int cb = lb % colblocks;
@@ -155,8 +180,8 @@ __global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
     const int s = rest / runs;
     const int t = cb * FIR_THREADS + threadIdx.x;
     const int t_wave = __builtin_amdgcn_readfirstlane(cb * FIR_THREADS + (threadIdx.x & ~63));
-    const int m0 = run * R;
-    const int mend = min(m0 + R, M);
+    const int m0 = mb + run * R;            // this launch covers spectra [mb, me)
+    const int mend = min(m0 + R, me);
 
     float h[T];
 #pragma unroll
@@ -172,8 +197,10 @@ __global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
 
     const uint8_t *rs = raw + int64_t(s) * raw_stride;
     const uint8_t *hs = hist + int64_t(s) * hist_stride;
-    float *gs = g + int64_t(s) * M * n2 + t;
+    float *gs = g + int64_t(s) * M * n2;
+    const __amdgpu_buffer_rsrc_t rg = make_rsrc(gs, uint32_t(int64_t(M) * n2 * 4));
     const int row_bytes = (n2 / 4) * 5;                       // 2n samples of 10 bits
+    const uint32_t t_bytes = uint32_t(t) * 4u;
 
     // X[i] holds the sample of row (g0 - T + 1 + i) at the current delay
     float X[2 * T - 1];
@@ -183,22 +210,43 @@ __global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
     int c_cur = -1;                                           // delay the window rows belong to
 
     for (int g0 = m0; g0 < mend; g0 += T) {
-        bool fast = g0 + T <= mend && c_cur >= 0;
+        // fast path: the whole group has one delay cg and reads no history;
+        // if cg differs from the delay of the window rows held in X, the
+        // T-1 older rows are reloaded together with the T new ones
+        const int cg = __builtin_amdgcn_readlane(c_lane, g0 - m0);
+        bool fast = g0 + T <= mend;
         if (fast) {
 #pragma unroll
-            for (int r = 0; r < T; ++r)
-                fast = fast && __builtin_amdgcn_readlane(c_lane, g0 - m0 + r) == c_cur;
-            // the group's new samples all lie in this call's chunk
-            fast = fast && int64_t(n2) * g0 - c_cur + t_wave >= 0;
+            for (int r = 1; r < T; ++r)
+                fast = fast && __builtin_amdgcn_readlane(c_lane, g0 - m0 + r) == cg;
         }
+        const bool refill = cg != c_cur;
+        fast = fast && int64_t(n2) * (refill ? g0 - T + 1 : g0) - cg + t_wave >= 0;
         if (fast) {
-            // rows g0 .. g0+T-1 of column t at delay c_cur
-            const int64_t i0 = int64_t(n2) * g0 - c_cur + t;
-            const uint32_t sh = 6u - ((uint32_t(i0) & 3u) << 1);
-            const uint8_t *p = rs + ((5 * i0) >> 2);
+            // rows g0 .. g0+T-1 of column t at delay cg: byte offsets
+            // (5 i0)/4 + r*row_bytes, same bit phase in every row
+            const int i0 = n2 * g0 - cg + t;
+            const uint32_t lo = 6u - ((uint32_t(i0) & 3u) << 1);
+            const uint32_t voff = uint32_t(5 * i0) >> 2;
+            // all loads first (raw 16-bit words parked in the window slots they
+            // will occupy), then the conversions
+            if (refill) {
+#pragma unroll
+                for (int k = 1; k < T; ++k)       // rows g0-k
+                    X[T - 1 - k] = __builtin_bit_cast(float, load_u16(rs, voff - uint32_t(k * row_bytes)));
+                c_cur = cg;
+            }
 #pragma unroll
             for (int r = 0; r < T; ++r)
-                X[T - 1 + r] = field10(p + int64_t(r) * row_bytes, sh);
+                X[T - 1 + r] = __builtin_bit_cast(float, load_u16(rs, voff + uint32_t(r * row_bytes)));
+            if (refill) {
+#pragma unroll
+                for (int i = 0; i + 1 < T; ++i)
+                    X[i] = field10(__builtin_bit_cast(uint32_t, X[i]), lo);
+            }
+#pragma unroll
+            for (int r = 0; r < T; ++r)
+                X[T - 1 + r] = field10(__builtin_bit_cast(uint32_t, X[T - 1 + r]), lo);
 #pragma unroll
             for (int r = 0; r < T; ++r) {
                 float acc = 0.f;
@@ -206,32 +254,44 @@ __global__ __launch_bounds__(FIR_THREADS) void fir_kernel(
                 for (int j = 0; j < T; ++j)
                     acc = fmaf(X[r + j], h[j], acc);
                 const int ok = __builtin_amdgcn_readlane(ok_lane, g0 - m0 + r);
-                gs[int64_t(g0 + r) * n2] = ok ? acc : 0.f;
+                store_f32(ok ? acc : 0.f, rg, t_bytes, uint32_t((g0 + r) * n2 * 4));
             }
         } else {
+            // general path, one spectrum at a time with a shifting window W of
+            // rows m-T+1 .. m; starts from the fast path's rows when the delay
+            // still matches, reloads all T rows when the delay changes.
+            float W[T];
 #pragma unroll
-            for (int r = 0; r < T; ++r) {
-                const int m = g0 + r;
-                if (m < mend) {
-                    const int c = __builtin_amdgcn_readlane(c_lane, m - m0);
-                    // index of window row j = 0 (row m-T+1), relative to this call's first sample
-                    const int64_t base = int64_t(n2) * (m - T + 1) - c + t;
-                    if (c != c_cur) {
-#pragma unroll
-                        for (int j = 0; j < T; ++j)
-                            X[r + j] = float(sample_at(rs, hs, base + int64_t(n2) * j, H));
-                        c_cur = c;
-                    } else {
-                        X[r + T - 1] = float(sample_at(rs, hs, base + int64_t(n2) * (T - 1), H));
-                    }
-                    float acc = 0.f;
+            for (int j = 0; j + 1 < T; ++j)
+                W[j + 1] = X[j];                      // rows g0-T+1 .. g0-1 -> W[1 .. T-1]
+            int cw = c_cur;
+#pragma unroll 1
+            for (int m = g0; m < min(g0 + T, mend); ++m) {
+                const int c = __builtin_amdgcn_readlane(c_lane, m - m0);
+                const int64_t base = int64_t(n2) * (m - T + 1) - c + t;   // row m-T+1
+                if (c != cw) {
 #pragma unroll
                     for (int j = 0; j < T; ++j)
-                        acc = fmaf(X[r + j], h[j], acc);
-                    const int ok = __builtin_amdgcn_readlane(ok_lane, m - m0);
-                    gs[int64_t(m) * n2] = ok ? acc : 0.f;
+                        W[j] = float(sample_at(rs, hs, base + int64_t(n2) * j, H));
+                    cw = c;
+                } else {
+#pragma unroll
+                    for (int j = 0; j + 1 < T; ++j)
+                        W[j] = W[j + 1];
+                    W[T - 1] = float(sample_at(rs, hs, base + int64_t(n2) * (T - 1), H));
                 }
+                float acc = 0.f;
+#pragma unroll
+                for (int j = 0; j < T; ++j)
+                    acc = fmaf(W[j], h[j], acc);
+                const int ok = __builtin_amdgcn_readlane(ok_lane, m - m0);
+                store_f32(ok ? acc : 0.f, rg, t_bytes, uint32_t(m * n2 * 4));
             }
+            // hand the window back: rows g0+1 .. g0+T-1 (meaningful only if the group was whole)
+#pragma unroll
+            for (int j = 0; j + 1 < T; ++j)
+                X[T + j] = W[j + 1];
+            c_cur = cw;
         }
         // rows g0+1 .. g0+T-1 become the first T-1 rows of the next group
 #pragma unroll
@@ -340,7 +400,9 @@ template <> struct Plan<4096> { static constexpr int P = 3; static constexpr int
 template <> struct Plan<8192> { static constexpr int P = 4; static constexpr int R[4] = {16, 16, 16, 2}; };
 
 // Host and device agree on the twiddle-table layout: for each pass p with
-// L_p = R_0 ... R_{p-1} > 1, a block [L_p][R_p - 1] of exp(-2 pi i j q / (L_p R_p)).
+// L_p = R_0 ... R_{p-1} > 1, a block [R_p - 1][L_p] of exp(-2 pi i j q / (L_p R_p))
+// (q-major, so the lanes of a wave, which hold consecutive j, read one
+// contiguous segment per q).
 template <int N>
 __host__ __device__ constexpr int tw_offset(int p)
 {
@@ -369,13 +431,11 @@ constexpr int lds_pad(int i) { return i + (i >> 4); }
 template <int N> constexpr int lds_len() { return N + N / 16; }
 
 // One Stockham pass (radix R, L = product of earlier radices) over one
-// polarization's n points held in LDS (or, for the first pass, read straight
-// from the float32 g of this spectrum: z[m] = g[2m] + i g[2m+1]).
+// polarization's n points held in LDS:
 //   butterfly b: inputs z[b + q n/R], twiddle exp(-2 pi i j q/(L R)) with
 //   j = b mod L, R-point DFT, outputs to (b - j) R + j + r L.
-template <int N, int R, int L, bool FIRST>
-__device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, const float2 *__restrict__ src,
-                                         int tp, const float2 *__restrict__ tw)
+template <int N, int R, int L>
+__device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, int tp, const float2 *__restrict__ tw)
 {
     constexpr int NB = N / R;              // butterflies per polarization
     constexpr int NTP = N / 16;            // threads per polarization
@@ -386,19 +446,16 @@ __device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, const float2 
         const int b = tp + u * NTP;
 #pragma unroll
         for (int q = 0; q < R; ++q)
-            v[u][q] = FIRST ? src[b + q * NB] : buf[lds_pad(b + q * NB)];
+            v[u][q] = buf[lds_pad(b + q * NB)];
     }
-    if (!FIRST)
-        __syncthreads();
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int b = tp + u * NTP;
         const int j = b % L;
-        if (L > 1) {
 #pragma unroll
-            for (int q = 1; q < R; ++q)
-                v[u][q] = cmul(v[u][q], tw[j * (R - 1) + q - 1]);
-        }
+        for (int q = 1; q < R; ++q)
+            v[u][q] = cmul(v[u][q], tw[(q - 1) * L + j]);
         Dft<R>::run(v[u]);
         const int base = (b - j) * R + j;
 #pragma unroll
@@ -408,34 +465,55 @@ __device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, const float2 
     __syncthreads();
 }
 
+// Passes 1.. of the plan (pass 0, radix 16 with L = 1, is done by the caller
+// on register-held input).
 template <int N, int P>
-__device__ __forceinline__ void fft_run(float2 *buf, const float2 *src, int tp, const float2 *tw_all)
+__device__ __forceinline__ void fft_rest(float2 *buf, int tp, const float2 *tw_all)
 {
     if constexpr (P < Plan<N>::P) {
         constexpr int R = Plan<N>::R[P];
         constexpr int L = tw_L<N>(P);
-        fft_pass<N, R, L, P == 0>(buf, src, tp, tw_all + tw_offset<N>(P));
-        fft_run<N, P + 1>(buf, src, tp, tw_all);
+        fft_pass<N, R, L>(buf, tp, tw_all + tw_offset<N>(P));
+        fft_rest<N, P + 1>(buf, tp, tw_all);
     }
 }
 
-
 // ---------------------------------------------------------------------------
 // Kernel 2: FFT + R2C untangle + fine delay/phase + gain + quantise + store.
-// One workgroup = (antenna a, spectrum F), n/8 threads: threads [0, n/16)
-// transform polarization 0, the rest polarization 1.
+// A workgroup (n/8 threads) takes IPW consecutive spectra of one antenna, one
+// after another: threads [0, n/16) transform polarization 0, the rest
+// polarization 1, 16 points each.  The next spectrum's input is loaded into
+// registers while the current one is transformed.  In int8 mode the IPW
+// results of a channel are kept in registers and written as one IPW*4-byte
+// store (they are adjacent in the heap layout).
 // ---------------------------------------------------------------------------
 
 enum { OUT_INT8 = 0, OUT_PREQUANT = 1 };
 
-template <int N, int MODE>
-__global__ __launch_bounds__(N / 8) void fft_post_kernel(
+// A zero the compiler cannot see through.  Offsetting loop-invariant table
+// pointers by it inside a loop keeps their loads in the loop instead of
+// being hoisted into registers (which would cost occupancy).
+__device__ __forceinline__ int opaque_zero()
+{
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
+
+template <int IPW> struct OutVec;
+template <> struct OutVec<1> { using T = uint32_t; };
+template <> struct OutVec<2> { using T = uint2; };
+template <> struct OutVec<4> { using T = uint4; };
+
+template <int N, int MODE, int IPW>
+__global__ __launch_bounds__(N / 8, (N / 8 >= 256 ? 4 : 1)) void fft_post_kernel(
     const float *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw_all, const float2 *__restrict__ untangle,
     int8_t *__restrict__ out, float2 *__restrict__ y_out, int *__restrict__ status,
-    int M, int S, int D)
+    int M, int S, int D, int mb, int me)
 {
+    static_assert(Plan<N>::R[0] == 16, "plans start with a radix-16 pass");
     constexpr int NT = N / 8;
     constexpr int NTP = N / 16;
     constexpr int NH = N / 64;             // coarse phase-table entries (k >> 6)
@@ -444,85 +522,131 @@ __global__ __launch_bounds__(N / 8) void fft_post_kernel(
     __shared__ float2 ph_hi[2][NH < 1 ? 1 : NH];
     __shared__ float2 ph_lo[2][64];
 
-    const int logical = xcd_logical(blockIdx.x, gridDim.x);
-    const int a = logical / M;
-    const int F = logical % M;
+    // this launch covers spectra [mb, me) of every antenna; mb and me - mb are
+    // multiples of IPW, so the IPW spectra of a workgroup share antenna a
+    const int item0 = xcd_logical(blockIdx.x, gridDim.x) * IPW;
+    const int a = item0 / (me - mb);
+    const int F0 = mb + item0 % (me - mb);
     const int tid = threadIdx.x;
     const int pol = tid / NTP;
     const int tp = tid % NTP;
 
-    // delay split and phase of both polarizations (wave-uniform work)
-    int c0, c1;
-    double tau0, tau1;
-    const int64_t sp0 = (int64_t(a) * 2 + 0) * M + F, sp1 = (int64_t(a) * 2 + 1) * M + F;
-    const bool ok0 = split_delay(delays[sp0], D, c0, tau0);
-    const bool ok1 = split_delay(delays[sp1], D, c1, tau1);
-    if ((!ok0 || !ok1) && tid == 0)
-        atomicOr(status, 1);
+    // z[m] = g[2m] + i g[2m+1] of (antenna a, this thread's polarization, spectrum F0 + it)
+    const float2 *src = reinterpret_cast<const float2 *>(g) + ((int64_t(a) * 2 + pol) * M + F0) * N;
 
-    // phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] * ph_lo[k & 63];
-    // arguments in revolutions, reduced in float64, sin/cos in float32.
-    {
-        constexpr double inv_two_pi = 0.15915494309189533577;
-        for (int e = tid; e < 2 * (NH + 64); e += NT) {
-            const int p = e / (NH + 64);
-            const int i = e % (NH + 64);
-            const double tau = p ? tau1 : tau0;
-            const double phi = phases[p ? sp1 : sp0];
-            double rev;
-            if (i < NH)
-                rev = phi * inv_two_pi - double(64 * i) * tau / double(2 * N);
-            else
-                rev = -double(i - NH) * tau / double(2 * N);
-            rev -= rint(rev);
-            float sn, cs;
-            sincospif(float(2.0 * rev), &sn, &cs);
-            if (i < NH)
-                ph_hi[p][i] = make_float2(cs, sn);
-            else
-                ph_lo[p][i - NH] = make_float2(cs, sn);
-        }
-    }
-
-    // forward n-point complex FFT of z[m] = g[2m] + i g[2m+1] per polarization
-    const float2 *src = reinterpret_cast<const float2 *>(g + ((int64_t(a) * 2 + pol) * M + F) * (2 * N));
-    fft_run<N, 0>(buf + pol * NP, src, tp, tw_all);
-
-    // post-processing: thread owns channels k = tid + NT i for both pols
+    uint32_t acc[8][IPW];                  // int8 words of channels tid + NT i, spectra F0 ..
     const float2 *gain0 = gains + (int64_t(a) * 2 + 0) * N;
     const float2 *gain1 = gains + (int64_t(a) * 2 + 1) * N;
+
+#pragma unroll 1
+    for (int it = 0; it < IPW; ++it) {
+        const int F = F0 + it;
+        float2 cur[16];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int k = tid + NT * i;
-        const int km = (N - k) & (N - 1);
-        const float2 w = untangle[k];                 // exp(-i pi k / n)
-        float2 Y[2];
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            const float2 zk = buf[p * NP + lds_pad(k)];
-            const float2 zm = buf[p * NP + lds_pad(km)];
-            // E = (Z[k] + conj Z[n-k]) / 2, O = (Z[k] - conj Z[n-k]) / (2i)
-            const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-            const float2 O = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-            const float2 X = cadd(E, cmul(w, O));
-            const float2 rot = cmul(ph_hi[p][k >> 6], ph_lo[p][k & 63]);
-            const float2 gk = (p ? gain1 : gain0)[k];
-            const bool ok = p ? ok1 : ok0;
-            Y[p] = ok ? cmul(gk, cmul(rot, X)) : make_float2(0.f, 0.f);
-        }
-        if (MODE == OUT_PREQUANT) {
-            y_out[((int64_t(a) * 2 + 0) * M + F) * N + k] = Y[0];
-            y_out[((int64_t(a) * 2 + 1) * M + F) * N + k] = Y[1];
-        } else {
-            uint32_t word = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float v = (e & 1) ? Y[e >> 1].y : Y[e >> 1].x;
-                const float q = fminf(fmaxf(rintf(v), -127.f), 127.f);   // half-even, saturate
-                word |= (uint32_t(int32_t(q)) & 0xFFu) << (8 * e);
+        for (int q = 0; q < 16; ++q)
+            cur[q] = src[int64_t(it) * N + tp + q * NTP];
+
+        // delay split and phase of both polarizations (wave-uniform work)
+        int c0, c1;
+        double tau0, tau1;
+        const int64_t sp0 = (int64_t(a) * 2 + 0) * M + F, sp1 = (int64_t(a) * 2 + 1) * M + F;
+        const bool ok0 = split_delay(delays[sp0], D, c0, tau0);
+        const bool ok1 = split_delay(delays[sp1], D, c1, tau1);
+        if ((!ok0 || !ok1) && tid == 0)
+            atomicOr(status, 1);
+
+        // phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] * ph_lo[k & 63]/(1/2);
+        // arguments in revolutions, reduced in float64, sin/cos in float32.
+        // ph_lo carries the factor 1/2 of the real-FFT untangle (exact).
+        {
+            constexpr double inv_two_pi = 0.15915494309189533577;
+            constexpr double inv_two_n = 0.5 / N;          // exact: N is a power of two
+            for (int e = tid; e < 2 * (NH + 64); e += NT) {
+                const int p = e / (NH + 64);
+                const int i = e % (NH + 64);
+                const double tau_rev = (p ? tau1 : tau0) * inv_two_n;
+                double rev;
+                if (i < NH)
+                    rev = phases[p ? sp1 : sp0] * inv_two_pi - double(64 * i) * tau_rev;
+                else
+                    rev = -double(i - NH) * tau_rev;
+                rev -= rint(rev);
+                float sn, cs;
+                sincospif(float(2.0 * rev), &sn, &cs);
+                if (i < NH)
+                    ph_hi[p][i] = make_float2(cs, sn);
+                else
+                    ph_lo[p][i - NH] = make_float2(0.5f * cs, 0.5f * sn);
             }
-            const int64_t idx = ((int64_t(a) * (M / S) + F / S) * N + k) * S + (F % S);
-            reinterpret_cast<uint32_t *>(out)[idx] = word;
+        }
+
+        // forward n-point complex FFT per polarization: pass 0 in registers
+        const int z0 = opaque_zero();
+        float2 *pb = buf + pol * NP;
+        Dft<16>::run(cur);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            pb[lds_pad(tp * 16 + r)] = cur[r];
+        __syncthreads();
+        fft_rest<N, 1>(pb, tp, tw_all + z0);
+        const float2 *unt = untangle + z0;
+        const float2 *gn0 = gain0 + z0, *gn1 = gain1 + z0;
+
+        // post-processing: thread owns channels k = tid + NT i for both pols
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = tid + NT * i;
+            const int km = (N - k) & (N - 1);
+            const float2 w = unt[k];                  // exp(-i pi k / n)
+            float2 Y[2];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const float2 zk = buf[p * NP + lds_pad(k)];
+                const float2 zm = buf[p * NP + lds_pad(km)];
+                // 2E = Z[k] + conj Z[n-k], 2O = (Z[k] - conj Z[n-k]) / i, 2X = 2E + w 2O
+                const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
+                const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
+                const float2 X2 = cadd(E2, cmul(w, O2));
+                const float2 rot = cmul(ph_hi[p][k >> 6], ph_lo[p][k & 63]);   // includes 1/2
+                const float2 gk = (p ? gn1 : gn0)[k];
+                const bool ok = p ? ok1 : ok0;
+                Y[p] = ok ? cmul(gk, cmul(rot, X2)) : make_float2(0.f, 0.f);
+            }
+            if (MODE == OUT_PREQUANT) {
+                y_out[((int64_t(a) * 2 + 0) * M + F) * N + k] = Y[0];
+                y_out[((int64_t(a) * 2 + 1) * M + F) * N + k] = Y[1];
+            } else {
+                uint32_t word = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float v = (e & 1) ? Y[e >> 1].y : Y[e >> 1].x;
+                    const float q = fminf(fmaxf(rintf(v), -127.f), 127.f);   // half-even, saturate
+                    word |= (uint32_t(int32_t(q)) & 0xFFu) << (8 * e);
+                }
+#pragma unroll
+                for (int j = 0; j + 1 < IPW; ++j)
+                    acc[i][j] = acc[i][j + 1];
+                acc[i][IPW - 1] = word;
+            }
+        }
+        __syncthreads();                          // buf and phase tables are reused
+    }
+
+    if (MODE == OUT_INT8) {
+        using V = typename OutVec<IPW>::T;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = tid + NT * i;
+            const int64_t idx = ((int64_t(a) * (M / S) + F0 / S) * N + k) * S + (F0 % S);
+            V v;
+            if constexpr (IPW == 1) {
+                v = acc[i][0];
+            } else if constexpr (IPW == 2) {
+                v = make_uint2(acc[i][0], acc[i][1]);
+            } else {
+                v = make_uint4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
+            }
+            *reinterpret_cast<V *>(reinterpret_cast<uint32_t *>(out) + idx) = v;
         }
     }
 }
@@ -617,7 +741,7 @@ std::vector<float2> make_twiddles()
                 // exp(-2 pi i j q / (L R)) from an exact integer angle index
                 const long double a = -2.0L * 3.141592653589793238462643383279503L
                                       * (long double)((int64_t)j * q) / (long double)(L * R);
-                tw[size_t(off) + size_t(j) * (R - 1) + (q - 1)] =
+                tw[size_t(off) + size_t(q - 1) * L + j] =
                     make_float2(float(std::cos(a)), float(std::sin(a)));
             }
     }
@@ -640,7 +764,8 @@ std::vector<float2> twiddles_for(int n)
 fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_EHIP; }
 
 template <int T>
-void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g)
+void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g,
+                  int mb, int me)
 {
     const int n2 = 2 * s->n;
     const int M = int(N / n2);
@@ -648,54 +773,61 @@ void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const doubl
     const int colblocks = n2 / FIR_THREADS;
     // runs of R spectra; R >= 2T keeps whole groups of T for the fast path
     int R = 64;
-    while (R > 2 * T && int64_t(streams) * ((M + R - 1) / R) * colblocks < 1024)
+    while (R > 2 * T && int64_t(streams) * ((me - mb + R - 1) / R) * colblocks < 1024)
         R /= 2;
-    const int runs = (M + R - 1) / R;
+    const int runs = (me - mb + R - 1) / R;
     const int64_t blocks = int64_t(streams) * runs * colblocks;
     hipLaunchKernelGGL((fir_kernel<T>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
                        raw, N * 5 / 4, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps, delays, g,
-                       n2, M, s->D, R, colblocks, runs);
+                       n2, M, s->D, R, colblocks, runs, mb, me);
 }
 
-void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g)
+void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g,
+                int mb, int me)
 {
     switch (s->Tk) {
-    case 4: launch_fir_T<4>(s, raw, N, delays, g); break;
-    case 8: launch_fir_T<8>(s, raw, N, delays, g); break;
-    case 16: launch_fir_T<16>(s, raw, N, delays, g); break;
-    case 24: launch_fir_T<24>(s, raw, N, delays, g); break;
-    case 32: launch_fir_T<32>(s, raw, N, delays, g); break;
+    case 4: launch_fir_T<4>(s, raw, N, delays, g, mb, me); break;
+    case 8: launch_fir_T<8>(s, raw, N, delays, g, mb, me); break;
+    case 16: launch_fir_T<16>(s, raw, N, delays, g, mb, me); break;
+    case 24: launch_fir_T<24>(s, raw, N, delays, g, mb, me); break;
+    case 32: launch_fir_T<32>(s, raw, N, delays, g, mb, me); break;
     }
 }
 
-template <int N>
-void launch_post_N(const fe_stream *s, int64_t Ns, const double *delays, const double *phases,
-                   const float *gains, int8_t *out, float *y_out)
+template <int N, int IPW>
+void launch_post_NI(const fe_stream *s, hipStream_t st, int M, const double *delays,
+                    const double *phases, const float *gains, int8_t *out, float *y_out, int mb, int me)
 {
-    const int M = int(Ns / (2 * N));
-    const unsigned blocks = unsigned(s->A * M);
+    const unsigned blocks = unsigned(s->A * (me - mb) / IPW);
     if (y_out)
-        hipLaunchKernelGGL((fft_post_kernel<N, OUT_PREQUANT>), dim3(blocks), dim3(N / 8), 0, s->stream,
+        hipLaunchKernelGGL((fft_post_kernel<N, OUT_PREQUANT, IPW>), dim3(blocks), dim3(N / 8), 0, st,
                            s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
                            s->d_untangle, out, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->S,
-                           s->D);
+                           s->D, mb, me);
     else
-        hipLaunchKernelGGL((fft_post_kernel<N, OUT_INT8>), dim3(blocks), dim3(N / 8), 0, s->stream,
+        hipLaunchKernelGGL((fft_post_kernel<N, OUT_INT8, IPW>), dim3(blocks), dim3(N / 8), 0, st,
                            s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
                            s->d_untangle, out, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->S,
-                           s->D);
+                           s->D, mb, me);
 }
 
-void launch_post(const fe_stream *s, int64_t Ns, const double *delays, const double *phases,
-                 const float *gains, int8_t *out, float *y_out)
+template <int N>
+void launch_post_N(const fe_stream *s, hipStream_t st, int M, const double *delays,
+                   const double *phases, const float *gains, int8_t *out, float *y_out, int mb, int me)
+{
+    launch_post_NI<N, 1>(s, st, M, delays, phases, gains, out, y_out, mb, me);
+}
+
+void launch_post(const fe_stream *s, hipStream_t st, int M, const double *delays,
+                 const double *phases, const float *gains, int8_t *out, float *y_out, int mb, int me)
 {
     switch (s->n) {
-    case 256: launch_post_N<256>(s, Ns, delays, phases, gains, out, y_out); break;
-    case 512: launch_post_N<512>(s, Ns, delays, phases, gains, out, y_out); break;
-    case 1024: launch_post_N<1024>(s, Ns, delays, phases, gains, out, y_out); break;
-    case 2048: launch_post_N<2048>(s, Ns, delays, phases, gains, out, y_out); break;
-    case 4096: launch_post_N<4096>(s, Ns, delays, phases, gains, out, y_out); break;
-    case 8192: launch_post_N<8192>(s, Ns, delays, phases, gains, out, y_out); break;
+    case 256: launch_post_N<256>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
+    case 512: launch_post_N<512>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
+    case 1024: launch_post_N<1024>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
+    case 2048: launch_post_N<2048>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
+    case 4096: launch_post_N<4096>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
+    case 8192: launch_post_N<8192>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
     }
 }
 
@@ -756,19 +888,20 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
     if (cur != s->device && hipSetDevice(s->device) != hipSuccess)
         return FE_EHIP;
     (void)hipGetLastError();
+    const int M = int(N / (2 * s->n));
     hipEvent_t *ev = nullptr;
     if (s->timing && size_t(s->ev_used + 1) * 4 <= s->ev.size())
         ev = &s->ev[size_t(s->ev_used++) * 4];
     if (ev)
         (void)hipEventRecord(ev[0], s->stream);
-    launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g);
+    launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g, 0, M);
     if (ev)
         (void)hipEventRecord(ev[1], s->stream);
     launch_history_update(s, raw, N);
     if (ev)
         (void)hipEventRecord(ev[2], s->stream);
     if (!g_out)
-        launch_post(s, N, delays, phases, gains, out, y_out);
+        launch_post(s, s->stream, M, delays, phases, gains, out, y_out, 0, M);
     if (ev)
         (void)hipEventRecord(ev[3], s->stream);
     st = hip_status(hipGetLastError());

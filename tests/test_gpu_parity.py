@@ -119,7 +119,8 @@ def test_unpack_bit_exact():
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,T,step", [(1024, 16, 5), (256, 4, 5), (4096, 16, 5), (512, 24, 5),
-                                      (2048, 3, 5), (1024, 16, 0), (256, 32, 0), (512, 8, 40)])
+                                      (2048, 3, 5), (1024, 16, 0), (256, 32, 0), (512, 8, 40),
+                                      (256, 16, 16), (1024, 8, 8), (512, 16, 48)])
 def test_fir_impulses_bit_exact(n, T, step):
     """One impulse per window: g must equal float32(value * h[u]) exactly,
     which pins the sample order, the coarse-delay index and the tap mapping.
