@@ -64,7 +64,7 @@ enum {
  *   max_delay         D_max >= 0, largest coarse delay accepted (samples)
  *   max_samples       largest N (samples per polarization) of one call,
  *                     a multiple of 2n*S_h, at most 2^28; sizes the
- *                     library's workspace (A*2*max_samples*4 bytes)
+ *                     library's workspace (A*2*max_samples*5 bytes)
  *   weights           HOST pointer to float32[2n*T], the prototype filter h;
  *                     copied to the device during fe_stream_create */
 typedef struct fe_config {
@@ -139,11 +139,13 @@ fe_status fe_stream_status(fe_stream *s);
  * device allocation; events are created by fe_stream_timing(s, 1), at most
  * 4096 calls are recorded between reads).  fe_stream_timing_read
  * synchronizes and returns, over the calls recorded since timing was enabled
- * or last read, the summed milliseconds of the FIR kernel (steps 1-3a) and of
- * the FFT/post-processing kernel (steps 3b-6) and the number of calls, then
- * starts a new accumulation.  Any pointer may be NULL. */
+ * or last read, the summed milliseconds of the FIR kernel (steps 1-3a), of
+ * the FFT/post-processing kernel (steps 3b-6 up to the int8 values) and of the
+ * corner turn into heaps, and the number of calls, then starts a new
+ * accumulation.  Any pointer may be NULL. */
 fe_status fe_stream_timing(fe_stream *s, int enable);
-fe_status fe_stream_timing_read(fe_stream *s, double *fir_ms, double *post_ms, int64_t *calls);
+fe_status fe_stream_timing_read(fe_stream *s, double *fir_ms, double *post_ms, double *turn_ms,
+                                int64_t *calls);
 
 /* Test hook for step 1 alone: unpack samples [first, first+count) of the
  * packed stream `raw` (device, at least (first+count)*10/8 rounded up bytes)

@@ -51,6 +51,14 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 // multiply by -i
 __device__ __forceinline__ float2 cmul_mi(float2 a) { return make_float2(a.y, -a.x); }
 
+// Non-temporal (streaming, read-once) load of a complex value.
+__device__ __forceinline__ float2 load_nt(const float2 *p)
+{
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f *>(p));
+    return make_float2(v.x, v.y);
+}
+
 // ---------------------------------------------------------------------------
 // Step 1: sample j (>= 0) of a packed, MSB-first 10-bit two's complement
 // stream.  The 10 bits of a sample lie in bytes 5j/4 and 5j/4 + 1, starting
@@ -143,7 +151,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
 // 32-bit integer: pass the bits, not a converted value).
 __device__ __forceinline__ void store_f32(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    // cache policy 2 = non-temporal: the filtered samples stream to memory
+    // without displacing the taps and input rows from L2
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 2);
 }
 
 // Unaligned 16-bit global load (little-endian) at byte `off` of a
@@ -188,12 +198,12 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
     for (int j = 0; j < T; ++j)
         h[j] = taps[t + n2 * j];
 
+    // delays are split per batch of B spectra (lane l: spectrum b0 + l); the
+    // next batch's delays are loaded one batch ahead
+    constexpr int B = (64 / T) * T;
     const int lane = threadIdx.x & 63;
-    int c_lane = 0, ok_lane = 0;
-    if (m0 + lane < mend) {
-        double tau;
-        ok_lane = split_delay(delays[int64_t(s) * M + m0 + lane], D, c_lane, tau) ? 1 : 0;
-    }
+    const double *ds = delays + int64_t(s) * M;
+    double d_next = (lane < B && m0 + lane < mend) ? ds[m0 + lane] : 0.0;
 
     const uint8_t *rs = raw + int64_t(s) * raw_stride;
     const uint8_t *hs = hist + int64_t(s) * hist_stride;
@@ -209,16 +219,25 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
         X[i] = 0.f;
     int c_cur = -1;                                           // delay the window rows belong to
 
-    for (int g0 = m0; g0 < mend; g0 += T) {
+    for (int b0 = m0; b0 < mend; b0 += B) {
+    const int bend = min(b0 + B, mend);
+    int c_lane = 0, ok_lane = 0;
+    if (lane < B && b0 + lane < bend) {
+        double tau;
+        ok_lane = split_delay(d_next, D, c_lane, tau) ? 1 : 0;
+    }
+    d_next = (lane < B && bend + lane < mend) ? ds[bend + lane] : 0.0;
+
+    for (int g0 = b0; g0 < bend; g0 += T) {
         // fast path: the whole group has one delay cg and reads no history;
         // if cg differs from the delay of the window rows held in X, the
         // T-1 older rows are reloaded together with the T new ones
-        const int cg = __builtin_amdgcn_readlane(c_lane, g0 - m0);
-        bool fast = g0 + T <= mend;
+        const int cg = __builtin_amdgcn_readlane(c_lane, g0 - b0);
+        bool fast = g0 + T <= bend;
         if (fast) {
 #pragma unroll
             for (int r = 1; r < T; ++r)
-                fast = fast && __builtin_amdgcn_readlane(c_lane, g0 - m0 + r) == cg;
+                fast = fast && __builtin_amdgcn_readlane(c_lane, g0 - b0 + r) == cg;
         }
         const bool refill = cg != c_cur;
         fast = fast && int64_t(n2) * (refill ? g0 - T + 1 : g0) - cg + t_wave >= 0;
@@ -253,7 +272,7 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
 #pragma unroll
                 for (int j = 0; j < T; ++j)
                     acc = fmaf(X[r + j], h[j], acc);
-                const int ok = __builtin_amdgcn_readlane(ok_lane, g0 - m0 + r);
+                const int ok = __builtin_amdgcn_readlane(ok_lane, g0 - b0 + r);
                 store_f32(ok ? acc : 0.f, rg, t_bytes, uint32_t((g0 + r) * n2 * 4));
             }
         } else {
@@ -266,8 +285,8 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
                 W[j + 1] = X[j];                      // rows g0-T+1 .. g0-1 -> W[1 .. T-1]
             int cw = c_cur;
 #pragma unroll 1
-            for (int m = g0; m < min(g0 + T, mend); ++m) {
-                const int c = __builtin_amdgcn_readlane(c_lane, m - m0);
+            for (int m = g0; m < min(g0 + T, bend); ++m) {
+                const int c = __builtin_amdgcn_readlane(c_lane, m - b0);
                 const int64_t base = int64_t(n2) * (m - T + 1) - c + t;   // row m-T+1
                 if (c != cw) {
 #pragma unroll
@@ -284,7 +303,7 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
 #pragma unroll
                 for (int j = 0; j < T; ++j)
                     acc = fmaf(W[j], h[j], acc);
-                const int ok = __builtin_amdgcn_readlane(ok_lane, m - m0);
+                const int ok = __builtin_amdgcn_readlane(ok_lane, m - b0);
                 store_f32(ok ? acc : 0.f, rg, t_bytes, uint32_t(m * n2 * 4));
             }
             // hand the window back: rows g0+1 .. g0+T-1 (meaningful only if the group was whole)
@@ -297,6 +316,7 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
 #pragma unroll
         for (int i = 0; i < T - 1; ++i)
             X[i] = X[i + T];
+    }
     }
 }
 
@@ -479,174 +499,163 @@ __device__ __forceinline__ void fft_rest(float2 *buf, int tp, const float2 *tw_a
 }
 
 // ---------------------------------------------------------------------------
-// Kernel 2: FFT + R2C untangle + fine delay/phase + gain + quantise + store.
-// A workgroup (n/8 threads) takes IPW consecutive spectra of one antenna, one
-// after another: threads [0, n/16) transform polarization 0, the rest
-// polarization 1, 16 points each.  The next spectrum's input is loaded into
-// registers while the current one is transformed.  In int8 mode the IPW
-// results of a channel are kept in registers and written as one IPW*4-byte
-// store (they are adjacent in the heap layout).
+// Kernel 2: FFT + real-FFT untangle + fine delay/phase + gain + quantise.
+// One workgroup of n/16 threads per (antenna, polarization, spectrum), 16
+// points per thread: radix-16 Stockham passes in LDS, the first one on the
+// registers loaded from g.  Each thread then finishes channel pairs
+// (2j, 2j+1), j = tid + (n/16) i.  In int8 mode the spectrum's n (re, im)
+// byte pairs go contiguously into a spectrum-major staging buffer
+// [A][2][M][n][2] (kernel 3 turns it into heaps); in prequant mode Y is
+// written instead.
 // ---------------------------------------------------------------------------
 
 enum { OUT_INT8 = 0, OUT_PREQUANT = 1 };
 
-// A zero the compiler cannot see through.  Offsetting loop-invariant table
-// pointers by it inside a loop keeps their loads in the loop instead of
-// being hoisted into registers (which would cost occupancy).
-__device__ __forceinline__ int opaque_zero()
+__device__ __forceinline__ uint32_t quant_pair(float re, float im)
 {
-    int z;
-    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-    return z;
+    // round half to even, saturate to [-127, 127], two int8 in the low 16 bits
+    const int32_t qr = int32_t(fminf(fmaxf(rintf(re), -127.f), 127.f));
+    const int32_t qi = int32_t(fminf(fmaxf(rintf(im), -127.f), 127.f));
+    return (uint32_t(qr) & 0xFFu) | ((uint32_t(qi) & 0xFFu) << 8);
 }
 
-template <int IPW> struct OutVec;
-template <> struct OutVec<1> { using T = uint32_t; };
-template <> struct OutVec<2> { using T = uint2; };
-template <> struct OutVec<4> { using T = uint4; };
-
-template <int N, int MODE, int IPW>
-__global__ __launch_bounds__(N / 8, (N / 8 >= 256 ? 4 : 1)) void fft_post_kernel(
+template <int N, int MODE>
+__global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kernel(
     const float *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw_all, const float2 *__restrict__ untangle,
-    int8_t *__restrict__ out, float2 *__restrict__ y_out, int *__restrict__ status,
-    int M, int S, int D, int mb, int me)
+    uint32_t *__restrict__ spec8, float2 *__restrict__ y_out, int *__restrict__ status,
+    int M, int D, int mb, int me)
 {
     static_assert(Plan<N>::R[0] == 16, "plans start with a radix-16 pass");
-    constexpr int NT = N / 8;
-    constexpr int NTP = N / 16;
+    constexpr int NT = N / 16;             // threads, 16 points each
     constexpr int NH = N / 64;             // coarse phase-table entries (k >> 6)
     constexpr int NP = lds_len<N>();
-    __shared__ float2 buf[2 * NP];
-    __shared__ float2 ph_hi[2][NH < 1 ? 1 : NH];
-    __shared__ float2 ph_lo[2][64];
+    __shared__ float2 buf[NP];
+    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[64];
 
-    // this launch covers spectra [mb, me) of every antenna; mb and me - mb are
-    // multiples of IPW, so the IPW spectra of a workgroup share antenna a
-    const int item0 = xcd_logical(blockIdx.x, gridDim.x) * IPW;
-    const int a = item0 / (me - mb);
-    const int F0 = mb + item0 % (me - mb);
+    // work item ((a (me - mb) + F - mb) * 2 + p): both pols of a spectrum adjacent
+    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    const int p = item & 1;
+    const int af = item >> 1;
+    const int a = af / (me - mb);
+    const int F = mb + af % (me - mb);
     const int tid = threadIdx.x;
-    const int pol = tid / NTP;
-    const int tp = tid % NTP;
+    const int64_t sp = (int64_t(a) * 2 + p) * M + F;          // stream spectrum
 
-    // z[m] = g[2m] + i g[2m+1] of (antenna a, this thread's polarization, spectrum F0 + it)
-    const float2 *src = reinterpret_cast<const float2 *>(g) + ((int64_t(a) * 2 + pol) * M + F0) * N;
-
-    uint32_t acc[8][IPW];                  // int8 words of channels tid + NT i, spectra F0 ..
-    const float2 *gain0 = gains + (int64_t(a) * 2 + 0) * N;
-    const float2 *gain1 = gains + (int64_t(a) * 2 + 1) * N;
-
-#pragma unroll 1
-    for (int it = 0; it < IPW; ++it) {
-        const int F = F0 + it;
-        float2 cur[16];
+    // z[m] = g[2m] + i g[2m+1]
+    const float2 *src = reinterpret_cast<const float2 *>(g) + sp * N;
+    float2 v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-            cur[q] = src[int64_t(it) * N + tp + q * NTP];
+    for (int q = 0; q < 16; ++q)
+        v[q] = load_nt(src + tid + q * NT);
 
-        // delay split and phase of both polarizations (wave-uniform work)
-        int c0, c1;
-        double tau0, tau1;
-        const int64_t sp0 = (int64_t(a) * 2 + 0) * M + F, sp1 = (int64_t(a) * 2 + 1) * M + F;
-        const bool ok0 = split_delay(delays[sp0], D, c0, tau0);
-        const bool ok1 = split_delay(delays[sp1], D, c1, tau1);
-        if ((!ok0 || !ok1) && tid == 0)
-            atomicOr(status, 1);
+    int c;
+    double tau;
+    const bool ok = split_delay(delays[sp], D, c, tau);
+    if (!ok && tid == 0)
+        atomicOr(status, 1);
 
-        // phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] * ph_lo[k & 63]/(1/2);
-        // arguments in revolutions, reduced in float64, sin/cos in float32.
-        // ph_lo carries the factor 1/2 of the real-FFT untangle (exact).
-        {
-            constexpr double inv_two_pi = 0.15915494309189533577;
-            constexpr double inv_two_n = 0.5 / N;          // exact: N is a power of two
-            for (int e = tid; e < 2 * (NH + 64); e += NT) {
-                const int p = e / (NH + 64);
-                const int i = e % (NH + 64);
-                const double tau_rev = (p ? tau1 : tau0) * inv_two_n;
-                double rev;
-                if (i < NH)
-                    rev = phases[p ? sp1 : sp0] * inv_two_pi - double(64 * i) * tau_rev;
-                else
-                    rev = -double(i - NH) * tau_rev;
-                rev -= rint(rev);
-                float sn, cs;
-                sincospif(float(2.0 * rev), &sn, &cs);
-                if (i < NH)
-                    ph_hi[p][i] = make_float2(cs, sn);
-                else
-                    ph_lo[p][i - NH] = make_float2(0.5f * cs, 0.5f * sn);
-            }
+    // phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] * 2 ph_lo[k & 63];
+    // arguments in revolutions, reduced in float64, sin/cos in float32.
+    // ph_lo carries the factor 1/2 of the real-FFT untangle (exact).
+    {
+        constexpr double inv_two_pi = 0.15915494309189533577;
+        constexpr double inv_two_n = 0.5 / N;          // exact: N is a power of two
+        const double tau_rev = tau * inv_two_n;
+        const double phi_rev = phases[sp] * inv_two_pi;
+        for (int i = tid; i < NH + 64; i += NT) {
+            double rev = i < NH ? phi_rev - double(64 * i) * tau_rev : -double(i - NH) * tau_rev;
+            rev -= rint(rev);
+            float sn, cs;
+            sincospif(float(2.0 * rev), &sn, &cs);
+            if (i < NH)
+                ph_hi[i] = make_float2(cs, sn);
+            else
+                ph_lo[i - NH] = make_float2(0.5f * cs, 0.5f * sn);
         }
-
-        // forward n-point complex FFT per polarization: pass 0 in registers
-        const int z0 = opaque_zero();
-        float2 *pb = buf + pol * NP;
-        Dft<16>::run(cur);
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            pb[lds_pad(tp * 16 + r)] = cur[r];
-        __syncthreads();
-        fft_rest<N, 1>(pb, tp, tw_all + z0);
-        const float2 *unt = untangle + z0;
-        const float2 *gn0 = gain0 + z0, *gn1 = gain1 + z0;
-
-        // post-processing: thread owns channels k = tid + NT i for both pols
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = tid + NT * i;
-            const int km = (N - k) & (N - 1);
-            const float2 w = unt[k];                  // exp(-i pi k / n)
-            float2 Y[2];
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                const float2 zk = buf[p * NP + lds_pad(k)];
-                const float2 zm = buf[p * NP + lds_pad(km)];
-                // 2E = Z[k] + conj Z[n-k], 2O = (Z[k] - conj Z[n-k]) / i, 2X = 2E + w 2O
-                const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
-                const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
-                const float2 X2 = cadd(E2, cmul(w, O2));
-                const float2 rot = cmul(ph_hi[p][k >> 6], ph_lo[p][k & 63]);   // includes 1/2
-                const float2 gk = (p ? gn1 : gn0)[k];
-                const bool ok = p ? ok1 : ok0;
-                Y[p] = ok ? cmul(gk, cmul(rot, X2)) : make_float2(0.f, 0.f);
-            }
-            if (MODE == OUT_PREQUANT) {
-                y_out[((int64_t(a) * 2 + 0) * M + F) * N + k] = Y[0];
-                y_out[((int64_t(a) * 2 + 1) * M + F) * N + k] = Y[1];
-            } else {
-                uint32_t word = 0;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float v = (e & 1) ? Y[e >> 1].y : Y[e >> 1].x;
-                    const float q = fminf(fmaxf(rintf(v), -127.f), 127.f);   // half-even, saturate
-                    word |= (uint32_t(int32_t(q)) & 0xFFu) << (8 * e);
-                }
-#pragma unroll
-                for (int j = 0; j + 1 < IPW; ++j)
-                    acc[i][j] = acc[i][j + 1];
-                acc[i][IPW - 1] = word;
-            }
-        }
-        __syncthreads();                          // buf and phase tables are reused
     }
 
-    if (MODE == OUT_INT8) {
-        using V = typename OutVec<IPW>::T;
+    // forward n-point complex FFT: pass 0 in registers, the rest in LDS
+    Dft<16>::run(v);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int k = tid + NT * i;
-            const int64_t idx = ((int64_t(a) * (M / S) + F0 / S) * N + k) * S + (F0 % S);
-            V v;
-            if constexpr (IPW == 1) {
-                v = acc[i][0];
-            } else if constexpr (IPW == 2) {
-                v = make_uint2(acc[i][0], acc[i][1]);
-            } else {
-                v = make_uint4(acc[i][0], acc[i][1], acc[i][2], acc[i][3]);
-            }
-            *reinterpret_cast<V *>(reinterpret_cast<uint32_t *>(out) + idx) = v;
+    for (int r = 0; r < 16; ++r)
+        buf[lds_pad(tid * 16 + r)] = v[r];
+    __syncthreads();
+    fft_rest<N, 1>(buf, tid, tw_all);
+
+    const float2 *gn = gains + (int64_t(a) * 2 + p) * N;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int j = tid + NT * i;
+        float2 Y[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int k = 2 * j + e;
+            const int km = (N - k) & (N - 1);
+            const float2 zk = buf[lds_pad(k)];
+            const float2 zm = buf[lds_pad(km)];
+            // 2E = Z[k] + conj Z[n-k], 2O = (Z[k] - conj Z[n-k]) / i, 2X = 2E + w 2O
+            const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
+            const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
+            const float2 X2 = cadd(E2, cmul(untangle[k], O2));       // w = exp(-i pi k / n)
+            const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);    // includes 1/2
+            Y[e] = ok ? cmul(gn[k], cmul(rot, X2)) : make_float2(0.f, 0.f);
+        }
+        if (MODE == OUT_PREQUANT) {
+            reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
+        } else {
+            spec8[sp * (N / 2) + j] = quant_pair(Y[0].x, Y[0].y) | (quant_pair(Y[1].x, Y[1].y) << 16);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 3: corner turn of the int8 spectra into heaps,
+//   [A][2][M][n][2]  ->  [A][M/S][n][S][2][2].
+// A workgroup moves a tile of 64 spectra x 64 channels of one antenna through
+// LDS: it reads 128-byte rows (one pol, one spectrum, 64 channels) and writes
+// runs of consecutive spectra of one channel (contiguous within a heap).
+// ---------------------------------------------------------------------------
+
+constexpr int CT = 64;                     // tile edge (spectra and channels)
+
+__global__ __launch_bounds__(256) void corner_turn_kernel(
+    const uint32_t *__restrict__ spec8, int8_t *__restrict__ out, int M, int n, int S,
+    int ftiles, int ktiles)
+{
+    // t16[f][2k + p] = (re, im) of channel k0+k, pol p, spectrum F0+f
+    __shared__ uint16_t t16[CT][2 * CT + 2];
+    const int b = blockIdx.x;
+    const int kt = b % ktiles;
+    const int rest = b / ktiles;
+    const int ft = rest % ftiles;
+    const int a = rest / ftiles;
+    const int F0 = ft * CT, k0 = kt * CT;
+    const int tid = threadIdx.x;
+
+    // read: row r = (f, p) holds 32 dwords (64 channels); lanes take a dword each
+    const int kk = (tid & 31) * 2;
+    for (int r = tid >> 5; r < 2 * CT; r += 256 / 32) {
+        const int f = r >> 1, p = r & 1;
+        const int F = F0 + f;
+        uint32_t w = 0;
+        if (F < M)
+            w = spec8[((int64_t(a) * 2 + p) * M + F) * (n / 2) + (k0 + kk) / 2];
+        t16[f][2 * kk + p] = uint16_t(w);
+        t16[f][2 * (kk + 1) + p] = uint16_t(w >> 16);
+    }
+    __syncthreads();
+
+    // write: lane = spectrum, so a wave stores 64 consecutive dwords of a channel
+    const int f = tid & (CT - 1);
+    const int F = F0 + f;
+    if (F < M) {
+        for (int k = tid >> 6; k < CT; k += 256 / CT) {
+            const uint32_t d = *reinterpret_cast<const uint32_t *>(&t16[f][2 * k]);
+            const int64_t idx = ((int64_t(a) * (M / S) + F / S) * n + k0 + k) * S + (F % S);
+            reinterpret_cast<uint32_t *>(out)[idx] = d;
         }
     }
 }
@@ -696,6 +705,8 @@ __global__ void unpack_kernel(const uint8_t *__restrict__ raw, int64_t first, in
 // Host side
 // ---------------------------------------------------------------------------
 
+constexpr int EV_PER_CALL = 5;
+
 struct fe_stream {
     int n, T, Tk, A, S, D, H;
     int64_t max_samples;
@@ -707,8 +718,9 @@ struct fe_stream {
     uint8_t *d_hist;        // [A*2][H*5/4]
     uint8_t *d_hist_tmp;    // same, used when a call is shorter than H
     float *d_g;             // [A*2][max_samples/(2n)][2n]
+    uint32_t *d_spec8;      // [A*2][max_samples/(2n)][n] (re, im) int8 pairs
     int *d_status;
-    // kernel timing (fe_stream_timing): 4 events per recorded call
+    // kernel timing (fe_stream_timing): EV_PER_CALL events per recorded call
     std::vector<hipEvent_t> ev;
     int ev_used;            // calls recorded since the last read
     bool timing;
@@ -771,10 +783,12 @@ void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const doubl
     const int M = int(N / n2);
     const int streams = 2 * s->A;
     const int colblocks = n2 / FIR_THREADS;
-    // runs of R spectra; R >= 2T keeps whole groups of T for the fast path
-    int R = 64;
-    while (R > 2 * T && int64_t(streams) * ((me - mb + R - 1) / R) * colblocks < 1024)
-        R /= 2;
+    // runs of R spectra (whole batches of B = (64/T)T); longer runs load the
+    // taps less often, shorter ones give more workgroups
+    constexpr int B = (64 / T) * T;
+    int R = 4 * B;
+    while (R > B && int64_t(streams) * ((me - mb + R - 1) / R) * colblocks < 2048)
+        R -= B;
     const int runs = (me - mb + R - 1) / R;
     const int64_t blocks = int64_t(streams) * runs * colblocks;
     hipLaunchKernelGGL((fir_kernel<T>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
@@ -794,41 +808,41 @@ void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double 
     }
 }
 
-template <int N, int IPW>
-void launch_post_NI(const fe_stream *s, hipStream_t st, int M, const double *delays,
-                    const double *phases, const float *gains, int8_t *out, float *y_out, int mb, int me)
-{
-    const unsigned blocks = unsigned(s->A * (me - mb) / IPW);
-    if (y_out)
-        hipLaunchKernelGGL((fft_post_kernel<N, OUT_PREQUANT, IPW>), dim3(blocks), dim3(N / 8), 0, st,
-                           s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
-                           s->d_untangle, out, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->S,
-                           s->D, mb, me);
-    else
-        hipLaunchKernelGGL((fft_post_kernel<N, OUT_INT8, IPW>), dim3(blocks), dim3(N / 8), 0, st,
-                           s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
-                           s->d_untangle, out, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->S,
-                           s->D, mb, me);
-}
-
 template <int N>
-void launch_post_N(const fe_stream *s, hipStream_t st, int M, const double *delays,
-                   const double *phases, const float *gains, int8_t *out, float *y_out, int mb, int me)
+void launch_post_N(const fe_stream *s, int M, const double *delays, const double *phases,
+                   const float *gains, float *y_out, int mb, int me)
 {
-    launch_post_NI<N, 1>(s, st, M, delays, phases, gains, out, y_out, mb, me);
+    const unsigned blocks = unsigned(s->A * (me - mb) * 2);
+    if (y_out)
+        hipLaunchKernelGGL((fft_post_kernel<N, OUT_PREQUANT>), dim3(blocks), dim3(N / 16), 0, s->stream,
+                           s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status,
+                           M, s->D, mb, me);
+    else
+        hipLaunchKernelGGL((fft_post_kernel<N, OUT_INT8>), dim3(blocks), dim3(N / 16), 0, s->stream,
+                           s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status,
+                           M, s->D, mb, me);
 }
 
-void launch_post(const fe_stream *s, hipStream_t st, int M, const double *delays,
-                 const double *phases, const float *gains, int8_t *out, float *y_out, int mb, int me)
+void launch_post(const fe_stream *s, int M, const double *delays, const double *phases,
+                 const float *gains, float *y_out, int mb, int me)
 {
     switch (s->n) {
-    case 256: launch_post_N<256>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
-    case 512: launch_post_N<512>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
-    case 1024: launch_post_N<1024>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
-    case 2048: launch_post_N<2048>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
-    case 4096: launch_post_N<4096>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
-    case 8192: launch_post_N<8192>(s, st, M, delays, phases, gains, out, y_out, mb, me); break;
+    case 256: launch_post_N<256>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 512: launch_post_N<512>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 1024: launch_post_N<1024>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 2048: launch_post_N<2048>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 4096: launch_post_N<4096>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 8192: launch_post_N<8192>(s, M, delays, phases, gains, y_out, mb, me); break;
     }
+}
+
+void launch_corner_turn(const fe_stream *s, int M, int8_t *out)
+{
+    const int ftiles = (M + CT - 1) / CT, ktiles = s->n / CT;
+    hipLaunchKernelGGL(corner_turn_kernel, dim3(unsigned(s->A * ftiles * ktiles)), dim3(256), 0,
+                       s->stream, s->d_spec8, out, M, s->n, s->S, ftiles, ktiles);
 }
 
 unsigned grid_for(int64_t work, int threads)
@@ -890,20 +904,23 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
     (void)hipGetLastError();
     const int M = int(N / (2 * s->n));
     hipEvent_t *ev = nullptr;
-    if (s->timing && size_t(s->ev_used + 1) * 4 <= s->ev.size())
-        ev = &s->ev[size_t(s->ev_used++) * 4];
-    if (ev)
-        (void)hipEventRecord(ev[0], s->stream);
+    if (s->timing && size_t(s->ev_used + 1) * EV_PER_CALL <= s->ev.size())
+        ev = &s->ev[size_t(s->ev_used++) * EV_PER_CALL];
+    auto mark = [&](int i) {
+        if (ev)
+            (void)hipEventRecord(ev[i], s->stream);
+    };
+    mark(0);
     launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g, 0, M);
-    if (ev)
-        (void)hipEventRecord(ev[1], s->stream);
+    mark(1);
     launch_history_update(s, raw, N);
-    if (ev)
-        (void)hipEventRecord(ev[2], s->stream);
+    mark(2);
     if (!g_out)
-        launch_post(s, s->stream, M, delays, phases, gains, out, y_out, 0, M);
-    if (ev)
-        (void)hipEventRecord(ev[3], s->stream);
+        launch_post(s, M, delays, phases, gains, y_out, 0, M);
+    mark(3);
+    if (!g_out && !y_out)
+        launch_corner_turn(s, M, out);
+    mark(4);
     st = hip_status(hipGetLastError());
     if (cur != s->device)
         (void)hipSetDevice(cur);
@@ -930,6 +947,7 @@ void free_stream(fe_stream *s)
     (void)hipFree(s->d_hist);
     (void)hipFree(s->d_hist_tmp);
     (void)hipFree(s->d_g);
+    (void)hipFree(s->d_spec8);
     (void)hipFree(s->d_status);
     delete s;
 }
@@ -983,6 +1001,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
               && hipMalloc(&s->d_hist, hist_bytes) == hipSuccess
               && hipMalloc(&s->d_hist_tmp, hist_bytes) == hipSuccess
               && hipMalloc(&s->d_g, g_floats * sizeof(float)) == hipSuccess
+              && hipMalloc(&s->d_spec8, size_t(streams) * size_t(cfg->max_samples)) == hipSuccess
               && hipMalloc(&s->d_status, sizeof(int)) == hipSuccess;
     if (!ok) {
         free_stream(s);
@@ -1088,7 +1107,7 @@ fe_status fe_stream_timing(fe_stream *s, int enable)
         return FE_OK;
     }
     if (s->ev.empty()) {
-        s->ev.assign(size_t(4) * 4096, nullptr);
+        s->ev.assign(size_t(EV_PER_CALL) * 4096, nullptr);
         for (hipEvent_t &e : s->ev)
             if (hipEventCreate(&e) != hipSuccess) {
                 free_events(s);
@@ -1100,26 +1119,30 @@ fe_status fe_stream_timing(fe_stream *s, int enable)
     return FE_OK;
 }
 
-fe_status fe_stream_timing_read(fe_stream *s, double *fir_ms, double *post_ms, int64_t *calls)
+fe_status fe_stream_timing_read(fe_stream *s, double *fir_ms, double *post_ms, double *turn_ms,
+                                int64_t *calls)
 {
     if (!s)
         return FE_EINVAL;
-    double a = 0.0, b = 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};
     if (s->ev_used > 0 && hipStreamSynchronize(s->stream) != hipSuccess)
         return FE_EHIP;
     for (int i = 0; i < s->ev_used; ++i) {
-        float x = 0.f, y = 0.f;
-        hipEvent_t *e = &s->ev[size_t(i) * 4];
-        if (hipEventElapsedTime(&x, e[0], e[1]) != hipSuccess
-            || hipEventElapsedTime(&y, e[2], e[3]) != hipSuccess)
-            return FE_EHIP;
-        a += x;
-        b += y;
+        hipEvent_t *e = &s->ev[size_t(i) * EV_PER_CALL];
+        const int from[3] = {0, 2, 3}, to[3] = {1, 3, 4};
+        for (int k = 0; k < 3; ++k) {
+            float x = 0.f;
+            if (hipEventElapsedTime(&x, e[from[k]], e[to[k]]) != hipSuccess)
+                return FE_EHIP;
+            acc[k] += x;
+        }
     }
     if (fir_ms)
-        *fir_ms = a;
+        *fir_ms = acc[0];
     if (post_ms)
-        *post_ms = b;
+        *post_ms = acc[1];
+    if (turn_ms)
+        *turn_ms = acc[2];
     if (calls)
         *calls = s->ev_used;
     s->ev_used = 0;

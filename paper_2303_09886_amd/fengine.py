@@ -65,6 +65,7 @@ def load_library(path: Optional[str] = None):
     L.fe_stream_timing.argtypes = [_vp, ctypes.c_int]
     L.fe_stream_timing.restype = _st
     L.fe_stream_timing_read.argtypes = [_vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     L.fe_stream_timing_read.restype = _st
     L.fe_debug_unpack10.argtypes = [_vp, _i64, _i64, _vp, _vp]
@@ -174,11 +175,12 @@ class Stream:
         _check(load_library().fe_stream_timing(self._h, 1 if enable else 0), "fe_stream_timing")
 
     def timing_read(self):
-        """(fir_ms, post_ms, calls) summed since the last read; synchronizes."""
-        a, b, c = ctypes.c_double(), ctypes.c_double(), _i64()
+        """(fir_ms, post_ms, turn_ms, calls) summed since the last read; synchronizes."""
+        a, b, t, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), _i64()
         _check(load_library().fe_stream_timing_read(self._h, ctypes.byref(a), ctypes.byref(b),
-                                                    ctypes.byref(c)), "fe_stream_timing_read")
-        return a.value, b.value, int(c.value)
+                                                    ctypes.byref(t), ctypes.byref(c)),
+               "fe_stream_timing_read")
+        return a.value, b.value, t.value, int(c.value)
 
     def _args(self, raw, n_samples, delays, phases=None, gains=None):
         import torch
