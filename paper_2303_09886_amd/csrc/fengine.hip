@@ -218,6 +218,24 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
     for (int i = 0; i < 2 * T - 1; ++i)
         X[i] = 0.f;
     int c_cur = -1;                                           // delay the window rows belong to
+    // outputs of the last fast group, stored only after the next group's
+    // loads are issued: loads and stores share one in-order wait counter, so
+    // storing first would make every group wait for the previous stores
+    // (the stores are unconditional so that the compiler's wait counts stay
+    // exact; with nothing pending the lane offset lies beyond the buffer's
+    // record count and the hardware drops the store)
+    constexpr uint32_t DROP = 0x80000000u;
+    float pend[T];
+#pragma unroll
+    for (int r = 0; r < T; ++r)
+        pend[r] = 0.f;
+    uint32_t pend_voff = DROP, pend_soff = 0;
+    auto flush = [&]() {
+#pragma unroll
+        for (int r = 0; r < T; ++r)
+            store_f32(pend[r], rg, pend_voff, pend_soff + uint32_t(r * n2 * 4));
+        pend_voff = DROP;
+    };
 
     for (int b0 = m0; b0 < mend; b0 += B) {
     const int bend = min(b0 + B, mend);
@@ -258,6 +276,8 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
 #pragma unroll
             for (int r = 0; r < T; ++r)
                 X[T - 1 + r] = __builtin_bit_cast(float, load_u16(rs, voff + uint32_t(r * row_bytes)));
+            __builtin_amdgcn_sched_barrier(0);    // keep the stores behind the loads
+            flush();
             if (refill) {
 #pragma unroll
                 for (int i = 0; i + 1 < T; ++i)
@@ -273,9 +293,12 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
                 for (int j = 0; j < T; ++j)
                     acc = fmaf(X[r + j], h[j], acc);
                 const int ok = __builtin_amdgcn_readlane(ok_lane, g0 - b0 + r);
-                store_f32(ok ? acc : 0.f, rg, t_bytes, uint32_t((g0 + r) * n2 * 4));
+                pend[r] = ok ? acc : 0.f;
             }
+            pend_voff = t_bytes;
+            pend_soff = uint32_t(g0 * n2 * 4);
         } else {
+            flush();
             // general path, one spectrum at a time with a shifting window W of
             // rows m-T+1 .. m; starts from the fast path's rows when the delay
             // still matches, reloads all T rows when the delay changes.
@@ -318,6 +341,7 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
             X[i] = X[i + T];
     }
     }
+    flush();
 }
 
 // ---------------------------------------------------------------------------
