@@ -4,6 +4,8 @@
 One step = one fe_channelize call over the whole workload: 4 antennas x 2
 pols x 2^24 packed 10-bit samples/pol, 4096 channels, 16 taps, int8
 channel-major output (all six steps of the path), inputs resident in HBM.
+The headline value is the FP32 path; the FP16 and BF16 matrix-core variants
+are timed the same way and reported under "variants".
 Three input/output buffer sets (about 302 MB each) rotate so no step is
 served from the 256 MB Infinity Cache.
 
@@ -48,23 +50,92 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_figures(shape: synth.Shape):
+def kernel_figures(shape: synth.Shape, prec: str = "fp32"):
     """Algorithmic bytes and flops per real input sample of each kernel.
 
-    fir:  reads the packed samples (10 bits) once, writes g (float32): 5.25 B;
-          2T flops (T multiply-adds).
-    post: reads g (float32), writes one int8 (re, im) pair per channel, i.e.
-          1 B per real sample: 5 B; n-point complex FFT 5 n log2 n / 2n =
-          2.5 log2 n, real-FFT untangle ~5, phase + gain + quantise ~9 flops.
+    fir:  reads the packed samples (10 bits) once, writes g: 1.25 B + 4 B
+          (float32; FP16 mode: 2 B); 2T flops (T multiply-adds).
+    post: reads g, writes one int8 (re, im) pair per channel, i.e. 1 B per
+          real sample: 4 B + 1 B (FP16 mode: 2 B + 1 B); n-point complex FFT
+          5 n log2 n / 2n = 2.5 log2 n, real-FFT untangle ~5, phase + gain +
+          quantise ~9 flops.
     turn: corner turn of the int8 spectra into heaps: 1 B in, 1 B out.
     """
     n, T = shape.n, shape.taps
     lg = int(np.log2(n))
+    gb = 2.0 if prec == "fp16" else 4.0
     return {
-        "fir": {"bytes": 1.25 + 4.0, "flops": 2.0 * T},
-        "post": {"bytes": 4.0 + 1.0, "flops": 2.5 * lg + 5.0 + 9.0},
+        "fir": {"bytes": 1.25 + gb, "flops": 2.0 * T},
+        "post": {"bytes": gb + 1.0, "flops": 2.5 * lg + 5.0 + 9.0},
         "turn": {"bytes": 2.0, "flops": 0.0},
     }
+
+
+KERNEL_NAMES = {
+    "fp32": {"fir": "fir_kernel<%(T)d>", "post": "fft_post_kernel<%(n)d>", "turn": "corner_turn_kernel"},
+    "fp16": {"fir": "fir_mfma_kernel<%(T)d,fp16>", "post": "fft_mfma_kernel<%(n)d,fp16>",
+             "turn": "corner_turn_kernel"},
+    "bf16": {"fir": "fir_mfma_kernel<%(T)d,bf16>", "post": "fft_mfma_kernel<%(n)d,bf16>",
+             "turn": "corner_turn_kernel"},
+}
+
+
+def measure(fe, shape, w, sets, dev_arrays, prec, steps, warmup):
+    """Time `steps` channelize calls of one stream at precision `prec`; then a
+    second, instrumented pass for the per-kernel durations."""
+    import torch
+    N, A, n = shape.samples, shape.antennas, shape.n
+    delays, phases, gains = dev_arrays
+    st = fe.Stream(n, shape.taps, A, w.weights, N, spectra_per_heap=shape.spectra_per_heap,
+                   max_delay=shape.max_delay, precision=prec)
+    log("%s: warmup %d steps" % (prec, warmup))
+    for i in range(warmup):
+        raw, out = sets[i % len(sets)]
+        st.channelize(raw, N, delays, phases, gains, out)
+    torch.cuda.synchronize()
+    log("%s: timing %d steps" % (prec, steps))
+    t0 = time.perf_counter()
+    for i in range(steps):
+        raw, out = sets[i % len(sets)]
+        st.channelize(raw, N, delays, phases, gains, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # per-kernel durations: a second pass with the library's HIP-event timing
+    # (kept out of the timed steps above)
+    st.timing(True)
+    for i in range(max(1, min(steps, 20))):
+        raw, out = sets[i % len(sets)]
+        st.channelize(raw, N, delays, phases, gains, out)
+    fir_ms, post_ms, turn_ms, calls = st.timing_read()
+    st.timing(False)
+    status = st.status()
+    st.close()
+    if status != fe.FE_OK:
+        log("warning: %s stream status %d" % (prec, status))
+    ms_step = (t1 - t0) * 1e3 / steps
+    samples = A * 2 * N
+    fig = kernel_figures(shape, prec)
+    avg = {"fir": fir_ms / max(calls, 1), "post": post_ms / max(calls, 1),
+           "turn": turn_ms / max(calls, 1)}
+    dom = max(avg, key=avg.get)
+    names = {k: v % {"T": 16 if shape.taps <= 16 else 32, "n": n} if prec != "fp32"
+             else v % {"T": shape.taps, "n": n} for k, v in KERNEL_NAMES[prec].items()}
+    dur_s = avg[dom] * 1e-3
+    achieved = fig[dom]["bytes"] * samples / dur_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(names[dom]),
+            "kernel": names[dom], "avg_ms": round(avg[dom], 4),
+            "algorithmic_bytes_per_launch": int(fig[dom]["bytes"] * samples)}
+    if prec == "fp32":
+        roof["fp32_tflops"] = round(fig[dom]["flops"] * samples / dur_s / 1e12, 2)
+        roof["fp32_frac_of_peak"] = round(fig[dom]["flops"] * samples / dur_s / 1e12 / FP32_PEAK_TFLOPS, 4)
+    kernels = {names[k]: {"avg_ms": round(avg[k], 4),
+                          "GBps": round(fig[k]["bytes"] * samples / (avg[k] * 1e-3) / 1e9, 1)}
+               for k in avg if avg[k] > 0}
+    value = samples / (ms_step * 1e-3) / 1e9
+    return {"value": round(value, 2), "ms_per_step": round(ms_step, 4),
+            "hbm_roofline_frac": round(value * PATH_BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
+            "roofline": roof, "kernels": kernels}
 
 
 def stored_traffic(kernel: str):
@@ -121,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=None,
                     help="spectra per antenna for the CPU baseline (default: all)")
+    ap.add_argument("--variants", default="fp16,bf16",
+                    help="matrix-core variants timed beside the FP32 path (comma list, '' for none)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -157,34 +230,12 @@ def main():
         sets.append((raw, out))
     torch.cuda.synchronize()
 
-    st = fe.Stream(n, shape.taps, A, w.weights, N, spectra_per_heap=S, max_delay=shape.max_delay)
-    log("warmup %d steps" % args.warmup)
-    for i in range(args.warmup):
-        raw, out = sets[i % len(sets)]
-        st.channelize(raw, N, delays, phases, gains, out)
-    torch.cuda.synchronize()
-
-    log("timing %d steps" % args.steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        raw, out = sets[i % len(sets)]
-        st.channelize(raw, N, delays, phases, gains, out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # per-kernel durations: a second pass with the library's HIP-event timing
-    # (kept out of the timed steps above)
-    st.timing(True)
-    ksteps = max(1, min(args.steps, 20))
-    for i in range(ksteps):
-        raw, out = sets[i % len(sets)]
-        st.channelize(raw, N, delays, phases, gains, out)
-    fir_ms, post_ms, turn_ms, calls = st.timing_read()
-    st.timing(False)
-    status = st.status()
-    st.close()
-    if status != fe.FE_OK:
-        log("warning: stream status %d" % status)
+    dev_arrays = (delays, phases, gains)
+    res = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup)
+    variants = {}
+    for prec in args.variants.split(",") if args.variants else []:
+        r = measure(fe, shape, w, sets, dev_arrays, prec, args.steps, args.warmup)
+        variants[prec + "_mfma"] = r
 
     if args.copy_calibration:
         a = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
@@ -193,27 +244,6 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    samples = A * 2 * N
-    value = samples / (ms_step * 1e-3) / 1e9
-    fig = kernel_figures(shape)
-    avg = {"fir": fir_ms / max(calls, 1), "post": post_ms / max(calls, 1),
-           "turn": turn_ms / max(calls, 1)}
-    dom = max(avg, key=avg.get)
-    names = {"fir": "fir_kernel<%d>" % shape.taps, "post": "fft_post_kernel<%d>" % n,
-             "turn": "corner_turn_kernel"}
-    dur_s = avg[dom] * 1e-3
-    achieved = fig[dom]["bytes"] * samples / dur_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(names[dom]),
-            "kernel": names[dom], "avg_ms": round(avg[dom], 4),
-            "algorithmic_bytes_per_launch": int(fig[dom]["bytes"] * samples),
-            "fp32_tflops": round(fig[dom]["flops"] * samples / dur_s / 1e12, 2),
-            "fp32_frac_of_peak": round(fig[dom]["flops"] * samples / dur_s / 1e12 / FP32_PEAK_TFLOPS, 4)}
-    kernels = {names[k]: {"avg_ms": round(avg[k], 4),
-                          "GBps": round(fig[k]["bytes"] * samples / (avg[k] * 1e-3) / 1e9, 1)}
-               for k in avg if avg[k] > 0}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -224,12 +254,12 @@ def main():
 
     rec = {
         "metric": METRIC,
-        "value": round(value, 2),
+        "value": res["value"],
         "unit": "Gsample/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -241,9 +271,10 @@ def main():
                    "antennas": A, "pols": 2, "samples_per_pol": N, "channels": n,
                    "taps": shape.taps, "spectra_per_heap": S, "max_delay": shape.max_delay,
                    "buffer_sets": args.sets},
-        "hbm_roofline_frac": round(value * PATH_BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
-        "roofline": roof,
-        "kernels": kernels,
+        "hbm_roofline_frac": res["hbm_roofline_frac"],
+        "roofline": res["roofline"],
+        "kernels": res["kernels"],
+        "variants": variants,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }

@@ -56,12 +56,30 @@ enum {
     FE_ESIZE = -5     /* n_samples larger than the stream's max_samples */
 };
 
+/* Arithmetic of the FIR and FFT (fe_config.precision).
+ *   FE_PREC_FP32  float32 throughout (the reference path).
+ *   FE_PREC_FP16  the FIR of Eq. (1) and the radix-16 DFT stages run on the
+ *                 matrix cores with FP16 operands and FP32 accumulation; the
+ *                 filtered samples pass between kernels as FP16.  The
+ *                 10-bit samples are exact in FP16; the taps are scaled by a
+ *                 power of two so that none falls into the FP16 subnormal
+ *                 range.  Pre-quantisation error ~4e-4 relative (normwise).
+ *   FE_PREC_BF16  the same contractions with BF16 operands, each split into
+ *                 a high and a low BF16 part (three products per term); the
+ *                 filtered samples pass as FP32.
+ * Twiddles, phases and the delay split are computed in FP64 in every mode.
+ * Sec. 3.5.1 of the paper keeps its FFT in FP32 because an FP16 FFT leaves
+ * data-dependent spurs near -75 dB; the reduced modes trade that for speed
+ * and are measured against the FP64 oracle stage by stage. */
+enum { FE_PREC_FP32 = 0, FE_PREC_FP16 = 1, FE_PREC_BF16 = 2 };
+
 /* Stream configuration, fixed at creation.
  *   n_channels        n: a power of two, 256 .. 8192
  *   taps              T: 1 .. 32
  *   n_antennas        A >= 1; every antenna has two polarizations
  *   spectra_per_heap  S_h >= 1 (256 in the paper, Sec. 2.2)
  *   max_delay         D_max >= 0, largest coarse delay accepted (samples)
+ *   precision         one of FE_PREC_* (0 = FP32)
  *   max_samples       largest N (samples per polarization) of one call,
  *                     a multiple of 2n*S_h, at most 2^28; sizes the
  *                     library's workspace (A*2*max_samples*5 bytes)
@@ -73,7 +91,7 @@ typedef struct fe_config {
     int32_t n_antennas;
     int32_t spectra_per_heap;
     int32_t max_delay;
-    int32_t reserved0;            /* must be 0 */
+    int32_t precision;
     int64_t max_samples;
     const float *weights;
 } fe_config;
@@ -125,7 +143,9 @@ fe_status fe_channelize_prequant(fe_stream *s, const uint8_t *raw, int64_t n_sam
 
 /* The same call stopped after the FIR (Eq. (1)):
  *   g_out   device float32 [A][2][M][2n], the filtered samples g of every
- *           spectrum (zeros where the delay was out of range).
+ *           spectrum (zeros where the delay was out of range); for an
+ *           FE_PREC_FP16 stream the values are the FP16-rounded ones the FFT
+ *           would read.
  * Updates the stream state exactly as fe_channelize does. */
 fe_status fe_channelize_fir(fe_stream *s, const uint8_t *raw, int64_t n_samples,
                             const double *delays, float *g_out);

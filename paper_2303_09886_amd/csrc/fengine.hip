@@ -543,6 +543,66 @@ __device__ __forceinline__ uint32_t quant_pair(float re, float im)
     return (uint32_t(qr) & 0xFFu) | ((uint32_t(qi) & 0xFFu) << 8);
 }
 
+// Per-spectrum phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] *
+// ph_lo[k & 63] / lo_scale.  Arguments in revolutions, reduced in float64,
+// sin/cos in float32.  ph_lo also carries `lo_scale` (a power of two: the
+// factor 1/2 of the real-FFT untangle and any FFT stage scaling).
+template <int N, int NT>
+__device__ __forceinline__ void phase_tables(float2 *ph_hi, float2 *ph_lo, double phi, double tau,
+                                             float lo_scale, int tid)
+{
+    constexpr int NH = N / 64;
+    constexpr double inv_two_pi = 0.15915494309189533577;
+    constexpr double inv_two_n = 0.5 / N;          // exact: N is a power of two
+    const double tau_rev = tau * inv_two_n;
+    const double phi_rev = phi * inv_two_pi;
+    for (int i = tid; i < NH + 64; i += NT) {
+        double rev = i < NH ? phi_rev - double(64 * i) * tau_rev : -double(i - NH) * tau_rev;
+        rev -= rint(rev);
+        float sn, cs;
+        sincospif(float(2.0 * rev), &sn, &cs);
+        if (i < NH)
+            ph_hi[i] = make_float2(cs, sn);
+        else
+            ph_lo[i - NH] = make_float2(lo_scale * cs, lo_scale * sn);
+    }
+}
+
+// Steps 3b-6 on one polarization's n-point complex FFT Z held in LDS (natural
+// order, lds_pad layout): real-FFT untangle, phase, gain, then either the
+// int8 pair store or the pre-quantisation store.  Thread tid finishes channel
+// pairs (2j, 2j+1), j = tid + NT i.
+template <int N, int NT, int MODE>
+__device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, const float2 *ph_hi,
+                                              const float2 *ph_lo, const float2 *__restrict__ untangle,
+                                              const float2 *__restrict__ gn, bool ok, int64_t sp, int tid,
+                                              uint32_t *__restrict__ spec8, float2 *__restrict__ y_out)
+{
+#pragma unroll
+    for (int i = 0; i < N / 2 / NT; ++i) {
+        const int j = tid + NT * i;
+        float2 Y[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int k = 2 * j + e;
+            const int km = (N - k) & (N - 1);
+            const float2 zk = buf[lds_pad(k)];
+            const float2 zm = buf[lds_pad(km)];
+            // 2E = Z[k] + conj Z[n-k], 2O = (Z[k] - conj Z[n-k]) / i, 2X = 2E + w 2O
+            const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
+            const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
+            const float2 X2 = cadd(E2, cmul(untangle[k], O2));       // w = exp(-i pi k / n)
+            const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);    // includes 1/2
+            Y[e] = ok ? cmul(gn[k], cmul(rot, X2)) : make_float2(0.f, 0.f);
+        }
+        if (MODE == OUT_PREQUANT) {
+            reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
+        } else {
+            spec8[sp * (N / 2) + j] = quant_pair(Y[0].x, Y[0].y) | (quant_pair(Y[1].x, Y[1].y) << 16);
+        }
+    }
+}
+
 template <int N, int MODE>
 __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kernel(
     const float *__restrict__ g, const double *__restrict__ delays,
@@ -580,26 +640,7 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
     const bool ok = split_delay(delays[sp], D, c, tau);
     if (!ok && tid == 0)
         atomicOr(status, 1);
-
-    // phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] * 2 ph_lo[k & 63];
-    // arguments in revolutions, reduced in float64, sin/cos in float32.
-    // ph_lo carries the factor 1/2 of the real-FFT untangle (exact).
-    {
-        constexpr double inv_two_pi = 0.15915494309189533577;
-        constexpr double inv_two_n = 0.5 / N;          // exact: N is a power of two
-        const double tau_rev = tau * inv_two_n;
-        const double phi_rev = phases[sp] * inv_two_pi;
-        for (int i = tid; i < NH + 64; i += NT) {
-            double rev = i < NH ? phi_rev - double(64 * i) * tau_rev : -double(i - NH) * tau_rev;
-            rev -= rint(rev);
-            float sn, cs;
-            sincospif(float(2.0 * rev), &sn, &cs);
-            if (i < NH)
-                ph_hi[i] = make_float2(cs, sn);
-            else
-                ph_lo[i - NH] = make_float2(0.5f * cs, 0.5f * sn);
-        }
-    }
+    phase_tables<N, NT>(ph_hi, ph_lo, phases[sp], tau, 0.5f, tid);
 
     // forward n-point complex FFT: pass 0 in registers, the rest in LDS
     Dft<16>::run(v);
@@ -609,30 +650,631 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
     __syncthreads();
     fft_rest<N, 1>(buf, tid, tw_all);
 
-    const float2 *gn = gains + (int64_t(a) * 2 + p) * N;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int j = tid + NT * i;
-        float2 Y[2];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int k = 2 * j + e;
-            const int km = (N - k) & (N - 1);
-            const float2 zk = buf[lds_pad(k)];
-            const float2 zm = buf[lds_pad(km)];
-            // 2E = Z[k] + conj Z[n-k], 2O = (Z[k] - conj Z[n-k]) / i, 2X = 2E + w 2O
-            const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
-            const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
-            const float2 X2 = cadd(E2, cmul(untangle[k], O2));       // w = exp(-i pi k / n)
-            const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);    // includes 1/2
-            Y[e] = ok ? cmul(gn[k], cmul(rot, X2)) : make_float2(0.f, 0.f);
+    post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
+                               tid, spec8, y_out);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core (MFMA) variant: the FIR and the radix-16 DFT stages as FP16 or
+// BF16 contractions with FP32 accumulation.  Everything else (delay split,
+// twiddle and phase generation in FP64 on the host or per spectrum, the
+// untangle, phase/gain, quantisation) is the FP32 path's.
+//
+// FP16 operands hold the 10-bit samples exactly; the taps are scaled by a
+// power of two 2^sc (undone on the FP32 result) so that small taps stay out
+// of the FP16 subnormal range.  BF16 has 8 significant bits, so operands are
+// split as x = hi + lo (both BF16) and a product is formed as
+// hi*hi + hi*lo + lo*hi (three MFMAs; the dropped lo*lo term is below 2^-16
+// relative).  The filtered samples g travel between the two kernels as FP16
+// for FP16 and as FP32 for BF16 (a single BF16 would cost 2^-9).
+// ---------------------------------------------------------------------------
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int PREC> struct Mx;
+
+template <> struct Mx<FE_PREC_FP16> {
+    typedef f16x8 op;
+    static constexpr bool split = false;
+    __device__ static f32x16 mm32(op a, op b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
+    __device__ static f32x4 mm16(op a, op b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+    __device__ static void put(op &hi, op &lo, int e, float x) { hi[e] = (_Float16)x; (void)lo; }
+};
+
+template <> struct Mx<FE_PREC_BF16> {
+    typedef bf16x8 op;
+    static constexpr bool split = true;
+    __device__ static f32x16 mm32(op a, op b, f32x16 c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+    __device__ static f32x4 mm16(op a, op b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+    __device__ static void put(op &hi, op &lo, int e, float x)
+    {
+        const __bf16 h = (__bf16)x;
+        hi[e] = h;
+        lo[e] = (__bf16)(x - (float)h);
+    }
+};
+
+// a*b accumulated into c at the variant's precision (split: hi*hi + hi*lo + lo*hi)
+template <int PREC>
+__device__ __forceinline__ f32x16 mma32(const typename Mx<PREC>::op &ah, const typename Mx<PREC>::op &al,
+                                        const typename Mx<PREC>::op &bh, const typename Mx<PREC>::op &bl,
+                                        f32x16 c)
+{
+    c = Mx<PREC>::mm32(ah, bh, c);
+    if constexpr (Mx<PREC>::split) {
+        c = Mx<PREC>::mm32(ah, bl, c);
+        c = Mx<PREC>::mm32(al, bh, c);
+    }
+    return c;
+}
+
+template <int PREC>
+__device__ __forceinline__ f32x4 mma16(const typename Mx<PREC>::op &ah, const typename Mx<PREC>::op &al,
+                                       const typename Mx<PREC>::op &bh, const typename Mx<PREC>::op &bl,
+                                       f32x4 c)
+{
+    c = Mx<PREC>::mm16(ah, bh, c);
+    if constexpr (Mx<PREC>::split) {
+        c = Mx<PREC>::mm16(ah, bl, c);
+        c = Mx<PREC>::mm16(al, bh, c);
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1M: the FIR of Eq. (1) as a banded Toeplitz contraction.
+//
+// For one column t and a block of 16 consecutive spectra F0' .. F0'+15 that
+// share the coarse delay c, with x_q = s[2n(F0' - TK + 1 + q) + t - c]:
+//   g[F0'+i][t] = sum_q W_t[i][q] x_q,   W_t[i][q] = h'[t + 2n(q - i)]
+// for 0 <= q - i < TK (h' = the taps zero-padded in front to TK), zero
+// elsewhere: a 16 x (16 + TK - 1) matrix, half of it zero.  One
+// v_mfma_f32_16x16x32 (K-step of 32 rows) takes W_t as A (16 spectra x 32
+// rows) and, as B, the 32-row windows of 16 such blocks (the batch): one
+// instruction forms 256 outputs of column t.
+//
+// Workgroup = one stream, 64 columns x 256 spectra (16 blocks); wave w owns
+// columns 16w .. 16w+15.  The input rows of the tile are unpacked once into
+// LDS as FP16 pairs of rows (the window rows of a column are contiguous), for
+// the union of the tile's delays.  Blocks whose spectra do not share one
+// delay are formed in several passes, one per delay value, each output
+// taking the pass of its own delay.  A tile whose delays spread wider than
+// the staging area reads its operands directly from memory instead.
+// ---------------------------------------------------------------------------
+
+constexpr int FM_COLS = 64;                // columns per tile
+constexpr int FM_SPEC = 256;               // spectra per tile (16 blocks)
+constexpr int FM_WMAX = 92;                // staged columns (23 groups of 4): 64 + delay spread + 3
+
+template <int TK> struct FirM {
+    static constexpr int KS = (TK + 15 + 31) / 32;         // 32-row K-steps
+    static constexpr int ROWS = 16 * 15 + 32 * KS;         // staged rows
+    static constexpr int RPW = ROWS / 2 + 1;               // dwords per staged column (odd)
+    static constexpr int ZL = 16 + 32 * KS;                // zero-padded tap vector length
+};
+
+enum { GOUT_F16 = 0, GOUT_F32 = 1 };
+
+template <int TK, int PREC, int GOUT>
+__global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
+    const uint8_t *__restrict__ raw, int64_t raw_stride, int64_t Ncall,
+    const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
+    const float *__restrict__ taps, float tap_scale, float out_scale,
+    const double *__restrict__ delays, void *__restrict__ gout,
+    int n2, int M, int D, int mb, int me, int ctiles, int ftiles)
+{
+    using P = FirM<TK>;
+    typedef typename Mx<PREC>::op op;
+    __shared__ uint32_t stage[FM_WMAX * P::RPW];             // [u][row pair] FP16 x 2
+    __shared__ uint16_t zt[Mx<PREC>::split ? 2 : 1][FM_COLS][P::ZL];   // tap vectors (hi, lo)
+    __shared__ int cdel[FM_SPEC];                            // coarse delay, -1 if invalid
+    __shared__ uint8_t pass_of[FM_SPEC];
+    __shared__ int pdel[16][16];                             // [block][pass] delay
+    __shared__ int red[3];                                   // cmin, cmax, passes
+
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int ct = lb % ctiles;
+    const int rest = lb / ctiles;
+    const int ft = rest % ftiles;
+    const int s = rest / ftiles;
+    const int t0 = ct * FM_COLS;
+    const int F0 = mb + ft * FM_SPEC;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint8_t *rs = raw + int64_t(s) * raw_stride;
+    const uint8_t *hs = hist + int64_t(s) * hist_stride;
+
+    // ---- delays of the tile's spectra
+    if (tid == 0) {
+        red[0] = 0x7fffffff;
+        red[1] = -1;
+        red[2] = 1;
+    }
+    {
+        const int F = F0 + tid;
+        int c = -1;
+        if (F < me) {
+            int cc;
+            double tau;
+            if (split_delay(delays[int64_t(s) * M + F], D, cc, tau))
+                c = cc;
         }
-        if (MODE == OUT_PREQUANT) {
-            reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
-        } else {
-            spec8[sp * (N / 2) + j] = quant_pair(Y[0].x, Y[0].y) | (quant_pair(Y[1].x, Y[1].y) << 16);
+        cdel[tid] = c;
+    }
+    // ---- tap vectors: zt[col][16 + j] = h'[t + 2n j] (scaled), zero elsewhere;
+    // lanes take consecutive columns (coalesced), all loads issued first
+    {
+        const int col = tid & 63, j0 = tid >> 6;
+        constexpr int JPT = (TK + 3) / 4;
+        float hv[JPT];
+#pragma unroll
+        for (int q = 0; q < JPT; ++q) {
+            const int j = j0 + 4 * q;
+            hv[q] = j < TK ? taps[(t0 + col) + int64_t(n2) * j] * tap_scale : 0.f;
+        }
+        for (int v = j0; v < P::ZL; v += 4)
+            if (v < 16 || v >= 16 + TK)
+                for (int part = 0; part < (Mx<PREC>::split ? 2 : 1); ++part)
+                    zt[part][col][v] = 0;
+#pragma unroll
+        for (int q = 0; q < JPT; ++q) {
+            const int j = j0 + 4 * q;
+            if (j < TK) {
+                const float h = hv[q];
+                if constexpr (Mx<PREC>::split) {
+                    const __bf16 hh = (__bf16)h;
+                    const __bf16 hl = (__bf16)(h - (float)hh);
+                    zt[0][col][16 + j] = __builtin_bit_cast(uint16_t, hh);
+                    zt[1][col][16 + j] = __builtin_bit_cast(uint16_t, hl);
+                } else {
+                    zt[0][col][16 + j] = __builtin_bit_cast(uint16_t, (_Float16)h);
+                }
+            }
         }
     }
+    __syncthreads();
+    if (cdel[tid] >= 0) {
+        atomicMin(&red[0], cdel[tid]);
+        atomicMax(&red[1], cdel[tid]);
+    }
+    // passes: block b's spectra in order; a new pass starts where the delay
+    // changes (invalid spectra keep the current pass and are zeroed later)
+    if (tid < 16) {
+        const int b = tid;
+        int cur = -1;
+        for (int i = 0; i < 16; ++i)
+            if (cdel[16 * b + i] >= 0) {
+                cur = cdel[16 * b + i];
+                break;
+            }
+        if (cur < 0)
+            cur = 0;
+        int p = 0;
+        pdel[b][0] = cur;
+        for (int i = 0; i < 16; ++i) {
+            const int c = cdel[16 * b + i];
+            if (c >= 0 && c != cur) {
+                ++p;
+                cur = c;
+                pdel[b][p] = cur;
+            }
+            pass_of[16 * b + i] = uint8_t(p);
+        }
+        for (int q = p + 1; q < 16; ++q)
+            pdel[b][q] = cur;
+        atomicMax(&red[2], p + 1);
+    }
+    __syncthreads();
+    int cmin = red[0], cmax = red[1];
+    if (cmax < 0)
+        cmin = cmax = 0;                                     // no valid spectrum
+    const int npass = red[2];
+    // staged columns start on a 4-sample group (5 whole bytes): staged column
+    // u holds sample 2n r + 4 gq0 + u of row r, gq0 = floor((t0 - cmax) / 4)
+    const int gq0 = (t0 - cmax) >> 2;                        // arithmetic shift = floor
+    const int u0 = (t0 - cmax) - 4 * gq0;                    // 0 .. 3
+    const int NGR = (FM_COLS + cmax - cmin + u0 + 3) >> 2;   // groups per staged row
+    const bool staged = 4 * NGR <= FM_WMAX;
+    const int64_t row0 = int64_t(F0) - TK + 1;               // call-relative row of staged row 0
+
+    // ---- stage rows [row0, row0 + ROWS) as FP16 row pairs.  Item (pr, q):
+    // group q of rows 2 pr and 2 pr + 1, each 4 samples in 5 bytes read as
+    // two aligned dwords (in range: every chunk and history row holds a
+    // multiple of 4 bytes).  All of a thread's loads are issued first.
+    if (staged) {
+        constexpr int IPT = (P::ROWS / 2 * (FM_WMAX / 4) + 255) / 256;
+        const int total = (P::ROWS / 2) * NGR;
+        const int64_t g_row = n2 >> 2;                       // groups per row
+        const int64_t hist_g = H >> 2;
+        uint32_t dw[IPT][2][2];
+        uint32_t off[IPT][2];
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const int it = tid + 256 * k;
+            const int pr = it / NGR, q = it - pr * NGR;
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                dw[k][h2][0] = dw[k][h2][1] = 0u;
+                off[k][h2] = 0u;
+                if (it < total) {
+                    const int64_t ga = g_row * (row0 + 2 * pr + h2) + gq0 + q;   // absolute group
+                    const uint8_t *base = nullptr;
+                    int64_t byte = 0;
+                    if (ga < 0) {
+                        base = hs;
+                        byte = 5 * (ga + hist_g);
+                    } else if (4 * ga < Ncall) {
+                        base = rs;
+                        byte = 5 * ga;
+                    }
+                    if (base) {
+                        const uint32_t *p32 = reinterpret_cast<const uint32_t *>(base + (byte & ~int64_t(3)));
+                        dw[k][h2][0] = p32[0];
+                        dw[k][h2][1] = p32[1];
+                        off[k][h2] = uint32_t(byte & 3);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const int it = tid + 256 * k;
+            if (it >= total)
+                continue;
+            const int pr = it / NGR, q = it - pr * NGR;
+            float x[2][4];
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const uint32_t o = off[k][h2];
+                // big-endian bytes b0..b3 and (b3, b4) of the group
+                const uint32_t be0 = __builtin_amdgcn_perm(dw[k][h2][1], dw[k][h2][0], 0x00010203u + 0x01010101u * o);
+                const uint32_t be1 = __builtin_amdgcn_perm(dw[k][h2][1], dw[k][h2][0],
+                                                           0x0C0C0000u | ((o + 3u) << 8) | (o + 4u));
+                x[h2][0] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 22u, 10u)));
+                x[h2][1] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 12u, 10u)));
+                x[h2][2] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 2u, 10u)));
+                x[h2][3] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be1), 0u, 10u)));
+            }
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) {
+                const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)x[0][c4]);
+                const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)x[1][c4]);
+                stage[(4 * q + c4) * P::RPW + pr] = lo | (hi << 16);
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- contraction: lane (r16 = lane % 16, kg = lane / 16)
+    //   A: W_t[i = r16][32 ks + 8 kg + e];  B: rows 16 b + 32 ks + 8 kg + e of block b = r16;
+    //   D: spectra 16 b + 4 kg + e of block b = r16
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int myb = r16;
+    int my_pass[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        my_pass[e] = pass_of[16 * myb + 4 * kg + e];
+    // two halves of 8 columns; each half's outputs are stored before the next
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        f32x4 acc[8];
+#pragma unroll
+        for (int cl = 0; cl < 8; ++cl) {
+            const int col = 16 * wave + 8 * half + cl;
+            const int t = t0 + col;
+            op ah[P::KS], al[P::KS];
+#pragma unroll
+            for (int ks = 0; ks < P::KS; ++ks) {
+                const int o = 16 + 32 * ks + 8 * kg - r16;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if constexpr (Mx<PREC>::split) {
+                        ah[ks][e] = __builtin_bit_cast(__bf16, zt[0][col][o + e]);
+                        al[ks][e] = __builtin_bit_cast(__bf16, zt[1][col][o + e]);
+                    } else {
+                        ah[ks][e] = __builtin_bit_cast(_Float16, zt[0][col][o + e]);
+                    }
+                }
+            }
+            f32x4 res = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+            for (int ps = 0; ps < npass; ++ps) {
+                // blocks without a valid spectrum carry delay 0: keep the read in the staged range
+                const int c = min(max(pdel[myb][ps], cmin), cmax);
+                f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < P::KS; ++ks) {
+                    const int rho = 16 * myb + 32 * ks + 8 * kg;
+                    op bh, bl;
+                    if (staged) {
+                        const int u = col + cmax - c + u0;
+                        const uint32_t *sp = stage + u * P::RPW + rho / 2;
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            const uint32_t v = sp[w];
+                            const float x0 = float(__builtin_bit_cast(_Float16, uint16_t(v)));
+                            const float x1 = float(__builtin_bit_cast(_Float16, uint16_t(v >> 16)));
+                            Mx<PREC>::put(bh, bl, 2 * w, x0);
+                            Mx<PREC>::put(bh, bl, 2 * w + 1, x1);
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int64_t i = int64_t(n2) * (row0 + rho + e) + t - c;
+                            const int x = i < Ncall ? sample_at(rs, hs, i, H) : 0;
+                            Mx<PREC>::put(bh, bl, e, float(x));
+                        }
+                    }
+                    d = mma16<PREC>(ah[ks], al[ks], bh, bl, d);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (my_pass[e] == ps)
+                        res[e] = d[e];
+            }
+            acc[cl] = res;
+        }
+
+        // outputs: lane holds spectra 16 b + 4 kg + e at 8 consecutive columns
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int fl = 16 * myb + 4 * kg + e;
+            const int F = F0 + fl;
+            if (F >= me)
+                continue;
+            const bool ok = cdel[fl] >= 0;
+            const int64_t base = (int64_t(s) * M + F) * n2 + t0 + 16 * wave + 8 * half;
+            if constexpr (GOUT == GOUT_F16) {
+                uint32_t w[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float v0 = ok ? acc[2 * q][e] * out_scale : 0.f;
+                    const float v1 = ok ? acc[2 * q + 1][e] * out_scale : 0.f;
+                    w[q] = uint32_t(__builtin_bit_cast(uint16_t, (_Float16)v0))
+                           | (uint32_t(__builtin_bit_cast(uint16_t, (_Float16)v1)) << 16);
+                }
+                *reinterpret_cast<u32x4 *>(static_cast<_Float16 *>(gout) + base) = u32x4{w[0], w[1], w[2], w[3]};
+            } else {
+                // FP32 store; for FP16 streams the value is the FP16-rounded one
+                f32x4 *dst = reinterpret_cast<f32x4 *>(static_cast<float *>(gout) + base);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    f32x4 v;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float x = ok ? acc[4 * q + r][e] * out_scale : 0.f;
+                        if constexpr (PREC == FE_PREC_FP16)
+                            x = float((_Float16)x);
+                        v[r] = x;
+                    }
+                    dst[q] = v;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2M: FFT + post-processing with the radix-16 stages on the matrix
+// cores.
+//
+// Stockham formulation over the n complex points z (z[m] = g[2m] + i g[2m+1]).
+// Stage s (R_s = n / 16^s points per sub-transform, R' = R_s / 16) takes
+// group gam in [0, n/16), reads its 16 inputs at
+//   in(gam, j) = (gam mod R') + R' (j + 16 (gam div R')),      j = 0..15,
+// forms the 16-point DFT, multiplies output d by exp(-2 pi i (gam mod R') d / R_s)
+// and writes it to out(gam, d) = gam + (n/16) d.  After the last stage the
+// points are in natural order.  As a matrix product: 32 groups at a time
+// (the MFMA's N), the 16 complex inputs interleaved (re, im) as K = 32, the
+// outputs as M = 32 rows (16 real parts, then 16 imaginary parts), so A is
+// the real 32 x 32 form of the DFT-16 matrix, scaled by 1/4 so that values
+// cannot grow out of FP16 range (the 4^stages is returned with the phase
+// table).  v_mfma_f32_32x32x16 takes K in two halves.  A leftover radix
+// (2, 4 or 8, when n is not a power of 16) runs in FP32 on the vector ALUs.
+// ---------------------------------------------------------------------------
+
+template <int N> struct MPlan {
+    static constexpr int S16 = N >= 4096 ? 3 : 2;           // matrix stages
+    static constexpr int RL = N >> (4 * S16);               // leftover radix: 1, 2, 4, 8
+    static constexpr int G = N / 16;                        // groups per matrix stage
+    static constexpr int NT = N / 16 >= 64 ? N / 16 : 64;   // threads
+    static constexpr int NW = NT / 64;
+    static constexpr int CB = (G + 31) / 32;                // 32-group column blocks
+    static constexpr int CPW = (CB + NW - 1) / NW;          // column blocks per wave
+};
+
+// R' of matrix stage s
+template <int N> __host__ __device__ constexpr int mstage_rn(int s)
+{
+    int r = N;
+    for (int i = 0; i <= s; ++i)
+        r /= 16;
+    return r;
+}
+
+// One matrix stage reading its inputs from LDS (stages >= 1) or from the
+// registers already loaded (stage 0), writing outputs back to LDS.
+template <int N, int PREC, int S>
+__device__ __forceinline__ void mfma_stage(float2 *__restrict__ buf, typename Mx<PREC>::op (&Bh)[MPlan<N>::CPW][2],
+                                           typename Mx<PREC>::op (&Bl)[MPlan<N>::CPW][2],
+                                           const typename Mx<PREC>::op (&Ah)[2],
+                                           const typename Mx<PREC>::op (&Al)[2],
+                                           const float2 *__restrict__ tw16, int wave, int lane)
+{
+    using P = MPlan<N>;
+    constexpr int RN = mstage_rn<N>(S);
+    constexpr bool TWID = RN > 1;
+    const int n32 = lane & 31, h = lane >> 5;
+    if constexpr (S > 0) {
+#pragma unroll
+        for (int u = 0; u < P::CPW; ++u) {
+            const int gam = 32 * (wave * P::CPW + u) + n32;
+            const bool valid = gam < P::G;
+#pragma unroll
+            for (int kap = 0; kap < 2; ++kap)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = 8 * kap + 4 * h + e;
+                    const int idx = (gam % RN) + RN * (j + 16 * (gam / RN));
+                    const float2 v = valid ? buf[lds_pad(idx)] : make_float2(0.f, 0.f);
+                    Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e, v.x);
+                    Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e + 1, v.y);
+                }
+        }
+    }
+    f32x16 acc[P::CPW];
+#pragma unroll
+    for (int u = 0; u < P::CPW; ++u) {
+        acc[u] = f32x16{};
+#pragma unroll
+        for (int kap = 0; kap < 2; ++kap)
+            acc[u] = mma32<PREC>(Ah[kap], Al[kap], Bh[u][kap], Bl[u][kap], acc[u]);
+    }
+    if constexpr (S > 0)
+        __syncthreads();                                    // every input read before any output lands
+#pragma unroll
+    for (int u = 0; u < P::CPW; ++u) {
+        const int gam = 32 * (wave * P::CPW + u) + n32;
+        if (gam >= P::G)
+            continue;
+        // lane holds outputs d = 8 (t / 4) + 4 h + t % 4: re in acc[t], im in acc[t + 8]
+        float2 tw[8];
+        if constexpr (TWID) {
+            const float4 *tp = reinterpret_cast<const float4 *>(tw16 + (int64_t(S) * P::G + gam) * 16);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float4 w0 = tp[(8 * q + 4 * h) / 2];
+                const float4 w1 = tp[(8 * q + 4 * h) / 2 + 1];
+                tw[4 * q + 0] = make_float2(w0.x, w0.y);
+                tw[4 * q + 1] = make_float2(w0.z, w0.w);
+                tw[4 * q + 2] = make_float2(w1.x, w1.y);
+                tw[4 * q + 3] = make_float2(w1.z, w1.w);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int d = 8 * (t / 4) + 4 * h + t % 4;
+            float2 y = make_float2(acc[u][t], acc[u][t + 8]);
+            if constexpr (TWID)
+                y = cmul(y, tw[t]);
+            buf[lds_pad(gam + P::G * d)] = y;
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int PREC, int S>
+__device__ __forceinline__ void mfma_stages(float2 *buf, typename Mx<PREC>::op (&Bh)[MPlan<N>::CPW][2],
+                                            typename Mx<PREC>::op (&Bl)[MPlan<N>::CPW][2],
+                                            const typename Mx<PREC>::op (&Ah)[2],
+                                            const typename Mx<PREC>::op (&Al)[2],
+                                            const float2 *tw16, int wave, int lane)
+{
+    if constexpr (S < MPlan<N>::S16) {
+        mfma_stage<N, PREC, S>(buf, Bh, Bl, Ah, Al, tw16, wave, lane);
+        mfma_stages<N, PREC, S + 1>(buf, Bh, Bl, Ah, Al, tw16, wave, lane);
+    }
+}
+
+template <int N, int PREC, int MODE>
+__global__ __launch_bounds__(MPlan<N>::NT) void fft_mfma_kernel(
+    const void *__restrict__ g, const double *__restrict__ delays,
+    const double *__restrict__ phases, const float2 *__restrict__ gains,
+    const float2 *__restrict__ tw16, const float2 *__restrict__ untangle,
+    const u32x4 *__restrict__ dft_a, uint32_t *__restrict__ spec8, float2 *__restrict__ y_out,
+    int *__restrict__ status, int M, int D, int mb, int me)
+{
+    using P = MPlan<N>;
+    typedef typename Mx<PREC>::op op;
+    constexpr int NT = P::NT;
+    constexpr int NH = N / 64;
+    __shared__ float2 buf[lds_len<N>()];
+    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[64];
+
+    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    const int p = item & 1;
+    const int af = item >> 1;
+    const int a = af / (me - mb);
+    const int F = mb + af % (me - mb);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n32 = lane & 31, h = lane >> 5;
+    const int64_t sp = (int64_t(a) * 2 + p) * M + F;
+
+    // stage-0 operands straight from g: in(gam, j) = gam + (n/16) j
+    op Bh[P::CPW][2], Bl[P::CPW][2];
+#pragma unroll
+    for (int u = 0; u < P::CPW; ++u) {
+        const int gam = 32 * (wave * P::CPW + u) + n32;
+        const bool valid = gam < P::G;
+#pragma unroll
+        for (int kap = 0; kap < 2; ++kap)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = 8 * kap + 4 * h + e;
+                if constexpr (PREC == FE_PREC_FP16) {
+                    const uint32_t w = valid ? static_cast<const uint32_t *>(g)[sp * N + gam + P::G * j] : 0u;
+                    Bh[u][kap][2 * e] = __builtin_bit_cast(_Float16, uint16_t(w));
+                    Bh[u][kap][2 * e + 1] = __builtin_bit_cast(_Float16, uint16_t(w >> 16));
+                } else {
+                    const float2 v = valid ? static_cast<const float2 *>(g)[sp * N + gam + P::G * j]
+                                           : make_float2(0.f, 0.f);
+                    Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e, v.x);
+                    Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e + 1, v.y);
+                }
+            }
+    }
+    // the real 32 x 32 DFT-16 matrix (scaled 1/4) as this lane's A operands
+    op Ah[2], Al[2];
+#pragma unroll
+    for (int kap = 0; kap < 2; ++kap) {
+        const u32x4 vh = dft_a[(kap * 2 + 0) * 64 + lane];
+        Ah[kap] = __builtin_bit_cast(op, vh);
+        if constexpr (Mx<PREC>::split) {
+            const u32x4 vl = dft_a[(kap * 2 + 1) * 64 + lane];
+            Al[kap] = __builtin_bit_cast(op, vl);
+        }
+    }
+
+    int c;
+    double tau;
+    const bool ok = split_delay(delays[sp], D, c, tau);
+    if (!ok && tid == 0)
+        atomicOr(status, 1);
+    constexpr float unscale = float(1 << (2 * P::S16));    // 4^stages
+    phase_tables<N, NT>(ph_hi, ph_lo, phases[sp], tau, 0.5f * unscale, tid);
+
+    mfma_stages<N, PREC, 0>(buf, Bh, Bl, Ah, Al, tw16, wave, lane);
+
+    if constexpr (P::RL > 1) {
+        // leftover radix RL in FP32: group gam reads RL gam + j, writes gam + (n/RL) d
+        constexpr int GR = N / P::RL;
+        constexpr int PER = GR / NT;
+        float2 v[PER][P::RL];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int gam = tid + NT * q;
+#pragma unroll
+            for (int j = 0; j < P::RL; ++j)
+                v[q][j] = buf[lds_pad(P::RL * gam + j)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int gam = tid + NT * q;
+            Dft<P::RL>::run(v[q]);
+#pragma unroll
+            for (int d = 0; d < P::RL; ++d)
+                buf[lds_pad(gam + GR * d)] = v[q][d];
+        }
+        __syncthreads();
+    }
+
+    post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
+                               tid, spec8, y_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -733,12 +1375,17 @@ constexpr int EV_PER_CALL = 5;
 
 struct fe_stream {
     int n, T, Tk, A, S, D, H;
+    int prec;               // FE_PREC_*
+    float tap_scale;        // FP16 mode: taps scaled by 2^sc on the matrix cores
+    float out_scale;        // 2^-sc, applied to the FIR's FP32 result
     int64_t max_samples;
     int device;
     hipStream_t stream;
     float *d_taps;          // [2n*Tk], zero-padded in front when Tk > T
     float2 *d_tw;           // FFT twiddle blocks
     float2 *d_untangle;     // exp(-i pi k / n)
+    float2 *d_tw16;         // matrix-stage twiddles [stage][group][16] (reduced modes)
+    uint32_t *d_dfta;       // DFT-16 A-operand images [K half][hi, lo][lane][8 x 16 bit]
     uint8_t *d_hist;        // [A*2][H*5/4]
     uint8_t *d_hist_tmp;    // same, used when a call is shorter than H
     float *d_g;             // [A*2][max_samples/(2n)][2n]
@@ -797,6 +1444,104 @@ std::vector<float2> twiddles_for(int n)
     }
 }
 
+// Matrix-core FIR tap counts: one 32-row K-step holds 16 spectra x 16 taps,
+// two hold up to 32 taps.
+int kernel_taps_mfma(int T) { return T <= 16 ? 16 : 32; }
+
+uint16_t f16_bits(float x)
+{
+    const _Float16 h = (_Float16)x;
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+float f16_value(uint16_t u)
+{
+    _Float16 h;
+    std::memcpy(&h, &u, 2);
+    return float(h);
+}
+uint16_t bf16_bits(float x)              // round to nearest even (finite x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+float bf16_value(uint16_t b)
+{
+    const uint32_t u = uint32_t(b) << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+// A operand of the matrix stages: the real 32 x 32 form of the DFT-16 matrix
+// W[d][j] = exp(-2 pi i dj/16), scaled by 1/4.  Row m < 16 gives Re Y_m, row
+// 16 + m gives Im Y_m; column 2j + c takes Re x_j (c = 0) or Im x_j (c = 1).
+// Lane l of K half kap holds A[l mod 32][16 kap + 8 (l div 32) + e], e < 8;
+// in split mode a second image holds the BF16 residuals.
+std::vector<uint32_t> make_dft_a(int prec)
+{
+    std::vector<uint32_t> img(size_t(2) * 2 * 64 * 4, 0u);
+    const long double pi = 3.141592653589793238462643383279503L;
+    for (int kap = 0; kap < 2; ++kap)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 8; ++e) {
+                const int m = lane % 32, kq = lane / 32;
+                const int k = 16 * kap + 8 * kq + e;
+                const int j = k / 2, c = k % 2, d = m % 16;
+                const long double th = 2.0L * pi * (long double)((d * j) % 16) / 16.0L;
+                const long double cs = std::cos(th), sn = std::sin(th);
+                const double val = double(0.25L * (m < 16 ? (c == 0 ? cs : sn) : (c == 0 ? -sn : cs)));
+                uint16_t hi, lo = 0;
+                if (prec == FE_PREC_FP16) {
+                    hi = f16_bits(float(val));
+                } else {
+                    hi = bf16_bits(float(val));
+                    lo = bf16_bits(float(val - double(bf16_value(hi))));
+                }
+                for (int part = 0; part < 2; ++part) {
+                    const uint16_t v = part == 0 ? hi : lo;
+                    const size_t word = (size_t(kap * 2 + part) * 64 + lane) * 4 + e / 2;
+                    img[word] |= uint32_t(v) << (16 * (e % 2));
+                }
+            }
+    return img;
+}
+
+// Matrix-stage twiddles: entry [s][gam][d] = exp(-2 pi i (gam mod R') d / R_s).
+template <int N>
+std::vector<float2> make_tw16()
+{
+    using P = MPlan<N>;
+    std::vector<float2> tw(size_t(P::S16) * P::G * 16);
+    const long double pi = 3.141592653589793238462643383279503L;
+    for (int st = 0; st < P::S16; ++st) {
+        const int rn = mstage_rn<N>(st), rs = 16 * rn;
+        for (int gam = 0; gam < P::G; ++gam)
+            for (int d = 0; d < 16; ++d) {
+                const int64_t q = (int64_t(gam % rn) * d) % rs;
+                const long double a = -2.0L * pi * (long double)q / (long double)rs;
+                tw[(size_t(st) * P::G + gam) * 16 + d] = make_float2(float(std::cos(a)), float(std::sin(a)));
+            }
+    }
+    return tw;
+}
+
+std::vector<float2> tw16_for(int n)
+{
+    switch (n) {
+    case 256: return make_tw16<256>();
+    case 512: return make_tw16<512>();
+    case 1024: return make_tw16<1024>();
+    case 2048: return make_tw16<2048>();
+    case 4096: return make_tw16<4096>();
+    case 8192: return make_tw16<8192>();
+    default: return {};
+    }
+}
+
 fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_EHIP; }
 
 template <int T>
@@ -820,9 +1565,42 @@ void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const doubl
                        n2, M, s->D, R, colblocks, runs, mb, me);
 }
 
-void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g,
-                int mb, int me)
+template <int TK, int PREC>
+void launch_fir_mfma_T(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays,
+                       void *g, bool g_f32, int mb, int me)
 {
+    const int n2 = 2 * s->n;
+    const int M = int(N / n2);
+    const int ctiles = n2 / FM_COLS;
+    const int ftiles = (me - mb + FM_SPEC - 1) / FM_SPEC;
+    const int64_t blocks = int64_t(2 * s->A) * ftiles * ctiles;
+    if (PREC == FE_PREC_FP16 && !g_f32)
+        hipLaunchKernelGGL((fir_mfma_kernel<TK, PREC, GOUT_F16>), dim3(unsigned(blocks)), dim3(256), 0,
+                           s->stream, raw, N * 5 / 4, N, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps,
+                           s->tap_scale, s->out_scale, delays, g, n2, M, s->D, mb, me, ctiles, ftiles);
+    else
+        hipLaunchKernelGGL((fir_mfma_kernel<TK, PREC, GOUT_F32>), dim3(unsigned(blocks)), dim3(256), 0,
+                           s->stream, raw, N * 5 / 4, N, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps,
+                           s->tap_scale, s->out_scale, delays, g, n2, M, s->D, mb, me, ctiles, ftiles);
+}
+
+void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g,
+                int mb, int me, bool g_out = false)
+{
+    if (s->prec != FE_PREC_FP32) {
+        if (s->prec == FE_PREC_FP16) {
+            if (s->Tk == 16)
+                launch_fir_mfma_T<16, FE_PREC_FP16>(s, raw, N, delays, g, g_out, mb, me);
+            else
+                launch_fir_mfma_T<32, FE_PREC_FP16>(s, raw, N, delays, g, g_out, mb, me);
+        } else {
+            if (s->Tk == 16)
+                launch_fir_mfma_T<16, FE_PREC_BF16>(s, raw, N, delays, g, g_out, mb, me);
+            else
+                launch_fir_mfma_T<32, FE_PREC_BF16>(s, raw, N, delays, g, g_out, mb, me);
+        }
+        return;
+    }
     switch (s->Tk) {
     case 4: launch_fir_T<4>(s, raw, N, delays, g, mb, me); break;
     case 8: launch_fir_T<8>(s, raw, N, delays, g, mb, me); break;
@@ -849,9 +1627,49 @@ void launch_post_N(const fe_stream *s, int M, const double *delays, const double
                            M, s->D, mb, me);
 }
 
+template <int N, int PREC>
+void launch_post_mfma_N(const fe_stream *s, int M, const double *delays, const double *phases,
+                        const float *gains, float *y_out, int mb, int me)
+{
+    const unsigned blocks = unsigned(s->A * (me - mb) * 2);
+    const u32x4 *dfta = reinterpret_cast<const u32x4 *>(s->d_dfta);
+    if (y_out)
+        hipLaunchKernelGGL((fft_mfma_kernel<N, PREC, OUT_PREQUANT>), dim3(blocks), dim3(MPlan<N>::NT), 0,
+                           s->stream, s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains),
+                           s->d_tw16, s->d_untangle, dfta, s->d_spec8, reinterpret_cast<float2 *>(y_out),
+                           s->d_status, M, s->D, mb, me);
+    else
+        hipLaunchKernelGGL((fft_mfma_kernel<N, PREC, OUT_INT8>), dim3(blocks), dim3(MPlan<N>::NT), 0,
+                           s->stream, s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains),
+                           s->d_tw16, s->d_untangle, dfta, s->d_spec8, reinterpret_cast<float2 *>(y_out),
+                           s->d_status, M, s->D, mb, me);
+}
+
+template <int PREC>
+void launch_post_mfma(const fe_stream *s, int M, const double *delays, const double *phases,
+                      const float *gains, float *y_out, int mb, int me)
+{
+    switch (s->n) {
+    case 256: launch_post_mfma_N<256, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 512: launch_post_mfma_N<512, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 1024: launch_post_mfma_N<1024, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 2048: launch_post_mfma_N<2048, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 4096: launch_post_mfma_N<4096, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 8192: launch_post_mfma_N<8192, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
+    }
+}
+
 void launch_post(const fe_stream *s, int M, const double *delays, const double *phases,
                  const float *gains, float *y_out, int mb, int me)
 {
+    if (s->prec == FE_PREC_FP16) {
+        launch_post_mfma<FE_PREC_FP16>(s, M, delays, phases, gains, y_out, mb, me);
+        return;
+    }
+    if (s->prec == FE_PREC_BF16) {
+        launch_post_mfma<FE_PREC_BF16>(s, M, delays, phases, gains, y_out, mb, me);
+        return;
+    }
     switch (s->n) {
     case 256: launch_post_N<256>(s, M, delays, phases, gains, y_out, mb, me); break;
     case 512: launch_post_N<512>(s, M, delays, phases, gains, y_out, mb, me); break;
@@ -935,7 +1753,7 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
             (void)hipEventRecord(ev[i], s->stream);
     };
     mark(0);
-    launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g, 0, M);
+    launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g, 0, M, g_out != nullptr);
     mark(1);
     launch_history_update(s, raw, N);
     mark(2);
@@ -968,6 +1786,8 @@ void free_stream(fe_stream *s)
     (void)hipFree(s->d_taps);
     (void)hipFree(s->d_tw);
     (void)hipFree(s->d_untangle);
+    (void)hipFree(s->d_tw16);
+    (void)hipFree(s->d_dfta);
     (void)hipFree(s->d_hist);
     (void)hipFree(s->d_hist_tmp);
     (void)hipFree(s->d_g);
@@ -982,7 +1802,9 @@ extern "C" {
 
 fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **out)
 {
-    if (!cfg || !out || !cfg->weights || cfg->reserved0 != 0)
+    if (!cfg || !out || !cfg->weights)
+        return FE_EINVAL;
+    if (cfg->precision != FE_PREC_FP32 && cfg->precision != FE_PREC_FP16 && cfg->precision != FE_PREC_BF16)
         return FE_EINVAL;
     const int n = cfg->n_channels, T = cfg->taps;
     if (!is_pow2(n) || n < 256 || n > 8192 || T < 1 || T > 32 || cfg->n_antennas < 1
@@ -999,14 +1821,31 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
         return FE_ENOMEM;
     s->n = n;
     s->T = T;
-    s->Tk = kernel_taps(T);
+    s->prec = cfg->precision;
+    s->Tk = s->prec == FE_PREC_FP32 ? kernel_taps(T) : kernel_taps_mfma(T);
+    s->tap_scale = s->out_scale = 1.f;
+    if (s->prec == FE_PREC_FP16) {
+        // scale the taps so that the largest lies in [2^14, 2^15)
+        float mx = 0.f;
+        for (int64_t i = 0; i < int64_t(2) * n * T; ++i)
+            mx = std::fmax(mx, std::fabs(cfg->weights[i]));
+        if (!(mx < 3.0e38f)) {                 // inf or NaN taps
+            delete s;
+            return FE_EINVAL;
+        }
+        if (mx > 0.f) {
+            const int sc = 14 - std::ilogb(mx);
+            s->tap_scale = std::ldexp(1.f, sc);
+            s->out_scale = std::ldexp(1.f, -sc);
+        }
+    }
     s->A = cfg->n_antennas;
     s->S = cfg->spectra_per_heap;
     s->D = cfg->max_delay;
     s->max_samples = cfg->max_samples;
     s->stream = static_cast<hipStream_t>(hip_stream);
     int64_t H = int64_t(2) * n * (s->Tk - 1) + s->D;
-    H = (H + 3) / 4 * 4;                      // whole bytes of packed samples
+    H = (H + 15) / 16 * 16;                   // whole dwords of packed samples
     s->H = int(H);
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
@@ -1019,7 +1858,18 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     const size_t hist_bytes = size_t(streams) * size_t(H * 5 / 4);
     const size_t g_floats = size_t(streams) * size_t(cfg->max_samples);
     std::vector<float2> tw = twiddles_for(n);
+    std::vector<float2> tw16;
+    std::vector<uint32_t> dfta;
+    if (s->prec != FE_PREC_FP32) {
+        tw16 = tw16_for(n);
+        dfta = make_dft_a(s->prec);
+    } else {
+        tw16.assign(1, make_float2(0.f, 0.f));
+        dfta.assign(4, 0u);
+    }
     bool ok = hipMalloc(&s->d_taps, taps_n * sizeof(float)) == hipSuccess
+              && hipMalloc(&s->d_tw16, tw16.size() * sizeof(float2)) == hipSuccess
+              && hipMalloc(&s->d_dfta, dfta.size() * sizeof(uint32_t)) == hipSuccess
               && hipMalloc(&s->d_tw, tw.size() * sizeof(float2)) == hipSuccess
               && hipMalloc(&s->d_untangle, size_t(n) * sizeof(float2)) == hipSuccess
               && hipMalloc(&s->d_hist, hist_bytes) == hipSuccess
@@ -1043,6 +1893,8 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     ok = hipMemcpy(s->d_taps, taps.data(), taps_n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess
          && hipMemcpy(s->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
          && hipMemcpy(s->d_untangle, unt.data(), size_t(n) * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
+         && hipMemcpy(s->d_tw16, tw16.data(), tw16.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
+         && hipMemcpy(s->d_dfta, dfta.data(), dfta.size() * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess
          && hipMemset(s->d_hist, 0, hist_bytes) == hipSuccess
          && hipMemset(s->d_hist_tmp, 0, hist_bytes) == hipSuccess
          && hipMemset(s->d_status, 0, sizeof(int)) == hipSuccess
@@ -1199,6 +2051,6 @@ const char *fe_strerror(fe_status status)
     }
 }
 
-int32_t fe_version(void) { return 100; }
+int32_t fe_version(void) { return 200; }
 
 }  // extern "C"

@@ -15,6 +15,8 @@ from typing import Optional
 from . import build as _build
 
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EHIP, FE_EDELAY, FE_ESIZE = 0, -1, -2, -3, -4, -5
+FE_PREC_FP32, FE_PREC_FP16, FE_PREC_BF16 = 0, 1, 2
+PRECISIONS = {"fp32": FE_PREC_FP32, "fp16": FE_PREC_FP16, "bf16": FE_PREC_BF16}
 
 
 class FEngineError(RuntimeError):
@@ -26,7 +28,7 @@ class FEngineError(RuntimeError):
 class _Config(ctypes.Structure):
     _fields_ = [("n_channels", ctypes.c_int32), ("taps", ctypes.c_int32),
                 ("n_antennas", ctypes.c_int32), ("spectra_per_heap", ctypes.c_int32),
-                ("max_delay", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("max_delay", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("max_samples", ctypes.c_int64), ("weights", ctypes.POINTER(ctypes.c_float))]
 
 
@@ -116,25 +118,29 @@ class Stream:
     """One fe_stream: A antennas x 2 polarizations with state across calls.
 
     ``weights`` is a host float32 array of 2n*T taps (copied at creation).
+    ``precision`` is "fp32" (default), "fp16" or "bf16" (the matrix-core
+    variants of the FIR and FFT, FE_PREC_* in the header).
     Work is enqueued on ``hip_stream`` (default: torch's current stream).
     """
 
     def __init__(self, n_channels: int, taps: int, n_antennas: int, weights,
                  max_samples: int, spectra_per_heap: int = 256, max_delay: int = 128,
-                 hip_stream=None):
+                 hip_stream=None, precision="fp32"):
         import numpy as np
         L = load_library()
         w = np.ascontiguousarray(weights, dtype=np.float32)
         if w.size != 2 * n_channels * taps:
             raise ValueError("weights must hold 2*n*T values")
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self._w = w
-        cfg = _Config(n_channels, taps, n_antennas, spectra_per_heap, max_delay, 0, max_samples,
+        cfg = _Config(n_channels, taps, n_antennas, spectra_per_heap, max_delay, prec, max_samples,
                       w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
         h = _vp()
         _check(L.fe_stream_create(ctypes.byref(cfg), _hip_stream(hip_stream), ctypes.byref(h)),
                "fe_stream_create")
         self._h = h
         self.n, self.taps, self.A = n_channels, taps, n_antennas
+        self.precision = prec
         self.S, self.max_delay, self.max_samples = spectra_per_heap, max_delay, max_samples
 
     # -- lifetime ---------------------------------------------------------

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_version_and_strerror(lib):
-    assert fe.version() == 100
+    assert fe.version() == 200
     for code in (fe.FE_OK, fe.FE_EINVAL, fe.FE_ENOMEM, fe.FE_EHIP, fe.FE_EDELAY, fe.FE_ESIZE):
         assert lib.fe_strerror(code)
     assert lib.fe_strerror(-99) == b"unknown status"
@@ -49,10 +49,10 @@ def test_version_and_strerror(lib):
 def _cfg(**kw):
     w = np.zeros(2 * kw.get("n_channels", 1024) * kw.get("taps", 16), dtype=np.float32)
     base = dict(n_channels=1024, taps=16, n_antennas=1, spectra_per_heap=256, max_delay=128,
-                reserved0=0, max_samples=1 << 20)
+                precision=0, max_samples=1 << 20)
     base.update(kw)
     c = _Config(base["n_channels"], base["taps"], base["n_antennas"], base["spectra_per_heap"],
-                base["max_delay"], base["reserved0"], base["max_samples"],
+                base["max_delay"], base["precision"], base["max_samples"],
                 w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
     return c, w
 
@@ -61,10 +61,18 @@ def _cfg(**kw):
     dict(n_channels=1000), dict(n_channels=128), dict(n_channels=16384), dict(taps=0),
     dict(taps=33), dict(n_antennas=0), dict(spectra_per_heap=0), dict(max_delay=-1),
     dict(max_samples=0), dict(max_samples=(1 << 20) + 2048), dict(max_samples=1 << 29),
-    dict(reserved0=1),
+    dict(precision=3), dict(precision=-1),
 ])
 def test_create_rejects_bad_config(lib, bad):
     cfg, _w = _cfg(**bad)
+    h = ctypes.c_void_p()
+    assert lib.fe_stream_create(ctypes.byref(cfg), None, ctypes.byref(h)) == fe.FE_EINVAL
+    assert not h.value
+
+
+def test_fp16_stream_rejects_non_finite_taps(lib):
+    cfg, w = _cfg(precision=fe.FE_PREC_FP16)
+    w[7] = np.inf
     h = ctypes.c_void_p()
     assert lib.fe_stream_create(ctypes.byref(cfg), None, ctypes.byref(h)) == fe.FE_EINVAL
     assert not h.value
