@@ -153,6 +153,105 @@ def stored_traffic(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def measure_batch(fe, steps: int, warmup: int, tune: bool = True):
+    """The 16-stream uneven batch: every step runs one call of each stream;
+    timed as one graph launch per step, and as the same calls issued stream
+    after stream on one HIP stream (no overlap) for comparison."""
+    import torch
+    shapes = synth.BATCH16
+    streams, bufs = [], []
+    for i, sh in enumerate(shapes):
+        w = synth.make_workload(sh, 100 + i)
+        M = sh.samples // (2 * sh.n)
+        st = fe.Stream(sh.n, sh.taps, 1, w.weights, sh.samples, spectra_per_heap=sh.spectra_per_heap,
+                       max_delay=sh.max_delay)
+        out = torch.empty((1, M // sh.spectra_per_heap, sh.n, sh.spectra_per_heap, 2, 2),
+                          dtype=torch.int8, device="cuda")
+        b = [torch.from_numpy(w.raw).cuda(), sh.samples, torch.from_numpy(w.delays).cuda(),
+             torch.from_numpy(w.phases).cuda(), torch.from_numpy(w.gains).cuda(), out]
+        del w
+        streams.append(st)
+        bufs.append(b)
+    torch.cuda.synchronize()
+    choices = [st.autotune(*b, iters=2) for st, b in zip(streams, bufs)] if tune else None
+    total = sum(2 * sh.samples for sh in shapes)
+    # sequential reference: each stream's call after the previous one
+    for _ in range(warmup):
+        for st, b in zip(streams, bufs):
+            st.channelize(*b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for st, b in zip(streams, bufs):
+            st.channelize(*b)
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3 / steps
+    batch = fe.Batch(streams)
+    batch.capture(bufs)
+    for _ in range(warmup):
+        batch.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.launch()
+    torch.cuda.synchronize()
+    g_ms = (time.perf_counter() - t0) * 1e3 / steps
+    batch.close()
+    for st in streams:
+        if st.status() != fe.FE_OK:
+            log("warning: batch member status %d" % st.status())
+        st.close()
+    return {"value": round(total / (g_ms * 1e-3) / 1e9, 2), "unit": "Gsample/s", "ms_per_step": round(g_ms, 4),
+            "sequential_ms_per_step": round(seq_ms, 4),
+            "sequential_value": round(total / (seq_ms * 1e-3) / 1e9, 2),
+            "streams": len(shapes), "samples_per_step": total, "fir_run_choices": choices,
+            "config": "16 single-antenna streams, channels 1024/4096/8192/32768, taps 8/16/24, "
+                      "2^22..2^24 samples/pol each, heaps of 64 spectra, one HIP-graph launch per step"}
+
+
+def measure_service(chunks: int = 24, seed: int = 3):
+    """Streaming service: one wide-band antenna (32768 channels, 16 taps),
+    chunks of k * 2^20 samples/pol (k uniform in 1..32).  First as a backlog
+    (every chunk waiting at t = 0: throughput), then with Poisson arrivals at
+    70% of that throughput (latency under load).  Chunk contents are cut from
+    one generated stretch of samples (timing does not depend on them)."""
+    from paper_2303_09886_amd import service
+    sh = synth.STREAM32K
+    unit = sh.samples                                  # 2^20 samples = 32 spectra
+    base = synth.make_workload(synth.Shape(n=sh.n, taps=sh.taps, antennas=1, samples=32 * unit,
+                                           spectra_per_heap=sh.spectra_per_heap), seed)
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(1, 33, size=chunks)
+
+    def requests(rate):
+        reqs, t = [], 0.0
+        for k in ks:
+            N = int(k) * unit
+            start = int(rng.integers(0, 33 - k)) * unit
+            raw, d, p = base.chunk(start, N)
+            if rate:
+                t += rng.exponential(N * 2 / rate)
+            reqs.append(service.Request(0, raw[0], N, d[0], p[0], base.gains[0], arrival=t))
+        return reqs
+
+    budget = 4 * service.chunk_device_bytes(sh.n, 32 * unit)
+    res = {}
+    for mode in ("backlog", "arrivals"):
+        svc = service.Service(sh.n, sh.taps, base.weights, feeds=1, max_chunk_samples=32 * unit,
+                              hbm_budget=budget, spectra_per_heap=sh.spectra_per_heap)
+        svc.run(requests(0), realtime=False)                 # warm-up (allocator, pinned slots)
+        rate = 0.7 * res["backlog"]["gsamples_per_s"] * 1e9 if mode == "arrivals" else 0
+        r = svc.run(requests(rate), realtime=(mode == "arrivals"))
+        svc.close()
+        res[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+        if rate:
+            res[mode]["offered_gsamples_per_s"] = round(rate / 1e9, 3)
+    res["config"] = ("1 antenna x 2 pols, 32768 channels (65536-pt real FFT), 16 taps, chunks of k*2^20 "
+                     "samples/pol with k uniform in 1..32, heaps of 16 spectra, HBM budget %d MB"
+                     % (budget >> 20))
+    return res
+
+
 def cpu_baseline(w: synth.Workload, spectra: int, threads: int):
     """Time the FP64 oracle on spectra [0, spectra) of every antenna, split
     over a thread pool (ctypes releases the GIL)."""
@@ -194,6 +293,8 @@ def main():
                     help="spectra per antenna for the CPU baseline (default: all)")
     ap.add_argument("--variants", default="fp16,bf16",
                     help="matrix-core variants timed beside the FP32 path (comma list, '' for none)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 16-stream batch measurement")
+    ap.add_argument("--no-service", action="store_true", help="skip the streaming-service measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -237,6 +338,18 @@ def main():
         r = measure(fe, shape, w, sets, dev_arrays, prec, args.steps, args.warmup)
         variants[prec + "_mfma"] = r
 
+    batched = None
+    if not args.no_batch:
+        del sets
+        torch.cuda.empty_cache()
+        log("batch: 16 uneven streams")
+        batched = measure_batch(fe, max(5, args.steps // 5), 2)
+
+    streaming = None
+    if not args.no_service:
+        log("streaming service: 32768 channels")
+        streaming = measure_service()
+
     if args.copy_calibration:
         a = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -275,6 +388,8 @@ def main():
         "roofline": res["roofline"],
         "kernels": res["kernels"],
         "variants": variants,
+        "batched": batched,
+        "streaming": streaming,
         "cpu_baseline": cpu,
         "device": torch.cuda.get_device_name(0),
     }

@@ -74,7 +74,9 @@ enum {
 enum { FE_PREC_FP32 = 0, FE_PREC_FP16 = 1, FE_PREC_BF16 = 2 };
 
 /* Stream configuration, fixed at creation.
- *   n_channels        n: a power of two, 256 .. 8192
+ *   n_channels        n: a power of two, 256 .. 32768 (FE_PREC_FP32), 256 .. 8192
+ *                     (FE_PREC_FP16, FE_PREC_BF16); above 8192 the FFT runs in two
+ *                     levels (a radix-16 pass in place, then n/16-point transforms)
  *   taps              T: 1 .. 32
  *   n_antennas        A >= 1; every antenna has two polarizations
  *   spectra_per_heap  S_h >= 1 (256 in the paper, Sec. 2.2)
@@ -173,6 +175,66 @@ fe_status fe_stream_timing_read(fe_stream *s, double *fir_ms, double *post_ms, d
  * `hip_stream`.  first and count >= 0. */
 fe_status fe_debug_unpack10(const uint8_t *raw, int64_t first, int64_t count,
                             int32_t *out, void *hip_stream);
+
+/* ---- Tuning ------------------------------------------------------------- */
+
+/* Time the stream's launch choices on the caller's buffers (an fe_channelize
+ * call's arguments; `iters` timed calls per candidate, HIP events on the
+ * stream's HIP stream) and keep the fastest.  The candidates are the FIR's
+ * run length -- how many consecutive 64-spectrum batches one workgroup
+ * filters, trading tap reloads against parallelism (1, 2, 4, 8 batches, or
+ * the per-launch default); reduced-precision streams have one candidate.
+ * The timing calls advance the stream like real calls, so the stream is
+ * reset (fe_stream_reset) before returning.  Synchronizes.  *choice (may be
+ * NULL) receives the chosen run length (0 = per-launch default). */
+fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples,
+                             const double *delays, const double *phases, const float *gains,
+                             int8_t *out, int iters, int *choice);
+
+/* Set the FIR run length directly (0 = per-launch default, else 1..64
+ * batches of 64 spectra). */
+fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches);
+
+/* ---- Batches of streams ------------------------------------------------ */
+
+/* One member's fe_channelize arguments. */
+typedef struct fe_call {
+    const uint8_t *raw;
+    int64_t n_samples;
+    const double *delays;
+    const double *phases;
+    const float *gains;
+    int8_t *out;
+} fe_call;
+
+/* A batch runs one call of every member stream (streams of any n, T, A and
+ * precision) as a unit: each member's kernels go to a fork HIP stream of its
+ * own, forked from and joined back into the batch's HIP stream, so the
+ * members' work overlaps on the device.  fe_batch_capture records that unit
+ * for fixed buffers into a HIP graph; each fe_batch_launch then replays it
+ * with a single graph launch (every member advancing by one call, state
+ * included).  The members stay owned by the caller and must outlive the
+ * batch; while a batch runs them, they must not be used directly. */
+typedef struct fe_batch fe_batch;
+
+/* members: `count` streams; hip_stream: the batch's HIP stream (NULL =
+ * default stream).  Creates the fork streams (default priority). */
+fe_status fe_batch_create(fe_stream *const *members, int count, void *hip_stream, fe_batch **out);
+
+/* Synchronize and release (not the members).  NULL is accepted. */
+fe_status fe_batch_destroy(fe_batch *b);
+
+/* Enqueue one call per member now (calls[i] for member i; no graph). */
+fe_status fe_batch_run(fe_batch *b, const fe_call *calls);
+
+/* Record one call per member with these buffers into the batch's graph
+ * (replacing an earlier one).  Synchronizes the batch stream first; nothing
+ * runs until fe_batch_launch.  The buffers must stay valid while the graph
+ * is used. */
+fe_status fe_batch_capture(fe_batch *b, const fe_call *calls);
+
+/* Replay the captured graph on the batch stream (FE_EINVAL if none). */
+fe_status fe_batch_launch(fe_batch *b);
 
 /* Human-readable text of a status code (static storage). */
 const char *fe_strerror(fe_status status);

@@ -535,12 +535,18 @@ __device__ __forceinline__ void fft_rest(float2 *buf, int tp, const float2 *tw_a
 
 enum { OUT_INT8 = 0, OUT_PREQUANT = 1 };
 
-__device__ __forceinline__ uint32_t quant_pair(float re, float im)
+// Four values to four int8 in one dword (byte i = value i): round half to
+// even, saturate to [-127, 127].  The rounded value plus 128 (exact) goes
+// into its byte as an unsigned 8-bit integer; flipping the top bit of every
+// byte then gives the two's complement code.
+__device__ __forceinline__ uint32_t quant4(float a, float b, float c, float d)
 {
-    // round half to even, saturate to [-127, 127], two int8 in the low 16 bits
-    const int32_t qr = int32_t(fminf(fmaxf(rintf(re), -127.f), 127.f));
-    const int32_t qi = int32_t(fminf(fmaxf(rintf(im), -127.f), 127.f));
-    return (uint32_t(qr) & 0xFFu) | ((uint32_t(qi) & 0xFFu) << 8);
+    uint32_t w = 0;
+    w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(rintf(a), -127.f, 127.f) + 128.f, 0u, w);
+    w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(rintf(b), -127.f, 127.f) + 128.f, 1u, w);
+    w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(rintf(c), -127.f, 127.f) + 128.f, 2u, w);
+    w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(rintf(d), -127.f, 127.f) + 128.f, 3u, w);
+    return w ^ 0x80808080u;
 }
 
 // Per-spectrum phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] *
@@ -598,7 +604,7 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
         if (MODE == OUT_PREQUANT) {
             reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
         } else {
-            spec8[sp * (N / 2) + j] = quant_pair(Y[0].x, Y[0].y) | (quant_pair(Y[1].x, Y[1].y) << 16);
+            spec8[sp * (N / 2) + j] = quant4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
         }
     }
 }
@@ -655,6 +661,120 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
 }
 
 // ---------------------------------------------------------------------------
+// Channel counts above what one workgroup's LDS holds (n = 16384, 32768):
+// the FFT in two levels (the decomposition behind the paper's Sec. 4 "unzip",
+// here with 16 as the first factor).
+//
+// Level 1 (fft_front_kernel): the first radix-16 Stockham stage, one thread
+// per group gam in [0, n/16): inputs z[gam + (n/16) j], outputs
+// U[d (n/16) + gam] = exp(-2 pi i gam d / n) DFT16(z[gam + (n/16) j])[d].
+// Inputs and outputs of a thread are the same 16 positions, so it runs in
+// place on the filtered samples.  Level 2: for each d, Z[d + 16 k'] is the
+// (n/16)-point DFT of U[d (n/16) + .] at k'.  Channel k = d + 16 k' pairs
+// with n - k in sub-transform (16 - d) mod 16, so fft_post_large_kernel
+// transforms the sub-transforms d and 16 - d together (nine rounds per
+// spectrum) and finishes both sets of channels.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void fft_front_kernel(float *__restrict__ g, const float2 *__restrict__ twf,
+                                                        int n, int M, int mb, int me, int A)
+{
+    const int gpt = n / 16;                                 // groups per spectrum
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t total = int64_t(A) * 2 * (me - mb) * gpt;
+    if (e >= total)
+        return;
+    const int gam = int(e % gpt);
+    const int64_t r = e / gpt;                              // (stream, spectrum - mb)
+    const int64_t sp = (r / (me - mb)) * M + mb + r % (me - mb);
+    float2 *z = reinterpret_cast<float2 *>(g) + sp * n;
+    float2 v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        v[j] = z[gam + gpt * j];
+    Dft<16>::run(v);
+    const float2 *tw = twf + int64_t(gam) * 16;
+#pragma unroll
+    for (int d = 0; d < 16; ++d)
+        z[gam + gpt * d] = d == 0 ? v[0] : cmul(v[d], tw[d]);
+}
+
+template <int NL, int MODE>
+__global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
+    const float *__restrict__ g, const double *__restrict__ delays,
+    const double *__restrict__ phases, const float2 *__restrict__ gains,
+    const float2 *__restrict__ tw_sub, const float2 *__restrict__ untangle,
+    uint32_t *__restrict__ spec8, float2 *__restrict__ y_out, int *__restrict__ status,
+    int M, int D, int mb, int me)
+{
+    constexpr int NS = NL / 16;                             // sub-transform length
+    constexpr int NTS = NS / 16;                            // threads per sub-transform
+    constexpr int NT = 2 * NTS;
+    constexpr int NH = NL / 64;
+    __shared__ float2 buf[2][lds_len<NS>()];
+    __shared__ float2 ph_hi[NH];
+    __shared__ float2 ph_lo[64];
+
+    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    const int p = item & 1;
+    const int af = item >> 1;
+    const int a = af / (me - mb);
+    const int F = mb + af % (me - mb);
+    const int tid = threadIdx.x;
+    const int half = tid / NTS, tp = tid % NTS;
+    const int64_t sp = (int64_t(a) * 2 + p) * M + F;
+    const float2 *u = reinterpret_cast<const float2 *>(g) + sp * NL;
+    const float2 *gn = gains + (int64_t(a) * 2 + p) * NL;
+    uint16_t *q16 = reinterpret_cast<uint16_t *>(spec8) + sp * NL;
+
+    int c;
+    double tau;
+    const bool ok = split_delay(delays[sp], D, c, tau);
+    if (!ok && tid == 0)
+        atomicOr(status, 1);
+    phase_tables<NL, NT>(ph_hi, ph_lo, phases[sp], tau, 0.5f, tid);
+
+    for (int dd = 0; dd <= 8; ++dd) {
+        const int dsel = half == 0 ? dd : (16 - dd) & 15;
+        float2 *bh = buf[half];
+        float2 v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = u[dsel * NS + tp + q * NTS];
+        Dft<16>::run(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            bh[lds_pad(tp * 16 + r)] = v[r];
+        __syncthreads();
+        fft_rest<NS, 1>(bh, tp, tw_sub);                    // both halves in step (same barriers)
+
+        // channels k = dsel + 16 k' of this half; partner n - k lies in
+        // sub-transform (16 - dsel) mod 16, held by the other half (or this
+        // one for dsel = 0, 8)
+        const bool dup = half == 1 && (dd == 0 || dd == 8);
+        if (!dup) {
+            for (int kk = tp; kk < NS; kk += NTS) {
+                const int k = dsel + 16 * kk;
+                const int km = (NL - k) & (NL - 1);
+                const int dm = km & 15, km2 = km >> 4;
+                const float2 zk = bh[lds_pad(kk)];
+                const float2 zm = buf[dm == dsel ? half : 1 - half][lds_pad(km2)];
+                const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
+                const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
+                const float2 X2 = cadd(E2, cmul(untangle[k], O2));
+                const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);
+                const float2 Y = ok ? cmul(gn[k], cmul(rot, X2)) : make_float2(0.f, 0.f);
+                if (MODE == OUT_PREQUANT)
+                    y_out[sp * NL + k] = Y;
+                else
+                    q16[k] = uint16_t(quant4(Y.x, Y.y, 0.f, 0.f));
+            }
+        }
+        __syncthreads();                                    // the buffers are refilled next round
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Matrix-core (MFMA) variant: the FIR and the radix-16 DFT stages as FP16 or
 // BF16 contractions with FP32 accumulation.  Everything else (delay split,
 // twiddle and phase generation in FP64 on the host or per spectrum, the
@@ -674,6 +794,15 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// two floats to an FP16 pair (round to nearest even; one v_cvt_pk_f16_f32)
+__device__ __forceinline__ uint32_t pack_f16x2(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{lo, hi}), f16x2));
+}
 
 template <int PREC> struct Mx;
 
@@ -769,8 +898,14 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
 {
     using P = FirM<TK>;
     typedef typename Mx<PREC>::op op;
+    constexpr int NPART = Mx<PREC>::split ? 2 : 1;          // tap parts (hi, lo)
     __shared__ uint32_t stage[FM_WMAX * P::RPW];             // [u][row pair] FP16 x 2
-    __shared__ uint16_t zt[Mx<PREC>::split ? 2 : 1][FM_COLS][P::ZL];   // tap vectors (hi, lo)
+    // tap vectors, 16-bit, [part][col][v]; built first in the staging area
+    uint16_t (*zt)[FM_COLS][P::ZL] = reinterpret_cast<uint16_t (*)[FM_COLS][P::ZL]>(stage);
+    static_assert(NPART * FM_COLS * P::ZL * 2 <= FM_WMAX * P::RPW * 4, "tap vectors fit the staging area");
+    // the same as overlapping pairs: zd[part][col][v] = (z[v], z[v + 1]), so
+    // that 8 consecutive taps from any offset are 4 aligned dwords
+    __shared__ uint32_t zd[NPART][FM_COLS][P::ZL];
     __shared__ int cdel[FM_SPEC];                            // coarse delay, -1 if invalid
     __shared__ uint8_t pass_of[FM_SPEC];
     __shared__ int pdel[16][16];                             // [block][pass] delay
@@ -867,6 +1002,13 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
             pdel[b][q] = cur;
         atomicMax(&red[2], p + 1);
     }
+    for (int e = tid; e < NPART * FM_COLS * P::ZL; e += 256) {
+        const int part = e / (FM_COLS * P::ZL);
+        const int col = (e / P::ZL) % FM_COLS, v = e % P::ZL;
+        const uint32_t lo = zt[part][col][v];
+        const uint32_t hi = v + 1 < P::ZL ? zt[part][col][v + 1] : 0u;
+        zd[part][col][v] = lo | (hi << 16);
+    }
     __syncthreads();
     int cmin = red[0], cmax = red[1];
     if (cmax < 0)
@@ -880,69 +1022,62 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
     const bool staged = 4 * NGR <= FM_WMAX;
     const int64_t row0 = int64_t(F0) - TK + 1;               // call-relative row of staged row 0
 
-    // ---- stage rows [row0, row0 + ROWS) as FP16 row pairs.  Item (pr, q):
-    // group q of rows 2 pr and 2 pr + 1, each 4 samples in 5 bytes read as
-    // two aligned dwords (in range: every chunk and history row holds a
-    // multiple of 4 bytes).  All of a thread's loads are issued first.
+    // ---- stage rows [row0, row0 + ROWS) as FP16 row pairs.  Thread
+    // (q = tid % 32, prs = tid / 32) takes group q (4 samples in 5 bytes) of
+    // row pairs prs, prs + 8, ...: each group read as two aligned dwords (in
+    // range: every chunk and history row is a multiple of 4 bytes), all of a
+    // thread's loads issued before the first conversion.
     if (staged) {
-        constexpr int IPT = (P::ROWS / 2 * (FM_WMAX / 4) + 255) / 256;
-        const int total = (P::ROWS / 2) * NGR;
-        const int64_t g_row = n2 >> 2;                       // groups per row
-        const int64_t hist_g = H >> 2;
-        uint32_t dw[IPT][2][2];
-        uint32_t off[IPT][2];
+        constexpr int PRS = P::ROWS / 2;                     // row pairs
+        constexpr int IT = (PRS + 7) / 8;
+        const int q = tid & 31, prs = tid >> 5;
+        const int gpr = n2 >> 2;                             // groups per row
+        const int hist_g = H >> 2;
+        const int ncall_g = int(Ncall >> 2);
+        const int ga0 = gpr * int(row0) + gq0 + q;           // group of (row0, q)
+        uint32_t dw[IT][2][2];
+        uint32_t off[IT][2];
+        if (q < NGR) {
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const int it = tid + 256 * k;
-            const int pr = it / NGR, q = it - pr * NGR;
+            for (int k = 0; k < IT; ++k) {
+                const int pr = prs + 8 * k;
 #pragma unroll
-            for (int h2 = 0; h2 < 2; ++h2) {
-                dw[k][h2][0] = dw[k][h2][1] = 0u;
-                off[k][h2] = 0u;
-                if (it < total) {
-                    const int64_t ga = g_row * (row0 + 2 * pr + h2) + gq0 + q;   // absolute group
-                    const uint8_t *base = nullptr;
-                    int64_t byte = 0;
-                    if (ga < 0) {
-                        base = hs;
-                        byte = 5 * (ga + hist_g);
-                    } else if (4 * ga < Ncall) {
-                        base = rs;
-                        byte = 5 * ga;
-                    }
-                    if (base) {
-                        const uint32_t *p32 = reinterpret_cast<const uint32_t *>(base + (byte & ~int64_t(3)));
-                        dw[k][h2][0] = p32[0];
-                        dw[k][h2][1] = p32[1];
-                        off[k][h2] = uint32_t(byte & 3);
-                    }
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const int ga = ga0 + gpr * (2 * pr + h2);
+                    const bool in_hist = ga < 0;
+                    const bool ok = pr < PRS && ga < ncall_g;
+                    const int byte = 5 * (in_hist ? ga + hist_g : ga);
+                    const uint8_t *base = in_hist ? hs : rs;
+                    // unconditional loads (offset 0 stands in for rows outside
+                    // the call; their words are zeroed after the load)
+                    const uint32_t *p32 = reinterpret_cast<const uint32_t *>(base) + (ok ? byte >> 2 : 0);
+                    const uint32_t w0 = p32[0], w1 = p32[1];
+                    dw[k][h2][0] = ok ? w0 : 0u;
+                    dw[k][h2][1] = ok ? w1 : 0u;
+                    off[k][h2] = uint32_t(byte & 3);
                 }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const int it = tid + 256 * k;
-            if (it >= total)
-                continue;
-            const int pr = it / NGR, q = it - pr * NGR;
-            float x[2][4];
+            for (int k = 0; k < IT; ++k) {
+                const int pr = prs + 8 * k;
+                if (pr >= PRS)
+                    break;
+                float x[2][4];
 #pragma unroll
-            for (int h2 = 0; h2 < 2; ++h2) {
-                const uint32_t o = off[k][h2];
-                // big-endian bytes b0..b3 and (b3, b4) of the group
-                const uint32_t be0 = __builtin_amdgcn_perm(dw[k][h2][1], dw[k][h2][0], 0x00010203u + 0x01010101u * o);
-                const uint32_t be1 = __builtin_amdgcn_perm(dw[k][h2][1], dw[k][h2][0],
-                                                           0x0C0C0000u | ((o + 3u) << 8) | (o + 4u));
-                x[h2][0] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 22u, 10u)));
-                x[h2][1] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 12u, 10u)));
-                x[h2][2] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 2u, 10u)));
-                x[h2][3] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be1), 0u, 10u)));
-            }
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const uint32_t o = off[k][h2];
+                    // big-endian bytes b0..b3 and (b3, b4) of the group
+                    const uint32_t be0 = __builtin_amdgcn_perm(dw[k][h2][1], dw[k][h2][0], 0x00010203u + 0x01010101u * o);
+                    const uint32_t be1 = __builtin_amdgcn_perm(dw[k][h2][1], dw[k][h2][0],
+                                                               0x0C0C0000u | ((o + 3u) << 8) | (o + 4u));
+                    x[h2][0] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 22u, 10u)));
+                    x[h2][1] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 12u, 10u)));
+                    x[h2][2] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 2u, 10u)));
+                    x[h2][3] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be1), 0u, 10u)));
+                }
 #pragma unroll
-            for (int c4 = 0; c4 < 4; ++c4) {
-                const uint32_t lo = __builtin_bit_cast(uint16_t, (_Float16)x[0][c4]);
-                const uint32_t hi = __builtin_bit_cast(uint16_t, (_Float16)x[1][c4]);
-                stage[(4 * q + c4) * P::RPW + pr] = lo | (hi << 16);
+                for (int c4 = 0; c4 < 4; ++c4)
+                    stage[(4 * q + c4) * P::RPW + pr] = pack_f16x2(x[0][c4], x[1][c4]);
             }
         }
     }
@@ -969,15 +1104,11 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
 #pragma unroll
             for (int ks = 0; ks < P::KS; ++ks) {
                 const int o = 16 + 32 * ks + 8 * kg - r16;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    if constexpr (Mx<PREC>::split) {
-                        ah[ks][e] = __builtin_bit_cast(__bf16, zt[0][col][o + e]);
-                        al[ks][e] = __builtin_bit_cast(__bf16, zt[1][col][o + e]);
-                    } else {
-                        ah[ks][e] = __builtin_bit_cast(_Float16, zt[0][col][o + e]);
-                    }
-                }
+                ah[ks] = __builtin_bit_cast(op, (u32x4{zd[0][col][o], zd[0][col][o + 2], zd[0][col][o + 4],
+                                                       zd[0][col][o + 6]}));
+                if constexpr (Mx<PREC>::split)
+                    al[ks] = __builtin_bit_cast(op, (u32x4{zd[NPART - 1][col][o], zd[NPART - 1][col][o + 2],
+                                                           zd[NPART - 1][col][o + 4], zd[NPART - 1][col][o + 6]}));
             }
             f32x4 res = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
@@ -992,13 +1123,19 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
                     if (staged) {
                         const int u = col + cmax - c + u0;
                         const uint32_t *sp = stage + u * P::RPW + rho / 2;
+                        const u32x4 v4 = {sp[0], sp[1], sp[2], sp[3]};
+                        if constexpr (PREC == FE_PREC_FP16) {
+                            bh = __builtin_bit_cast(op, v4);            // staged FP16 pairs are the operand
+                        } else {
 #pragma unroll
-                        for (int w = 0; w < 4; ++w) {
-                            const uint32_t v = sp[w];
-                            const float x0 = float(__builtin_bit_cast(_Float16, uint16_t(v)));
-                            const float x1 = float(__builtin_bit_cast(_Float16, uint16_t(v >> 16)));
-                            Mx<PREC>::put(bh, bl, 2 * w, x0);
-                            Mx<PREC>::put(bh, bl, 2 * w + 1, x1);
+                            for (int w = 0; w < 4; ++w) {
+                                // (scalar conversions: a vector FP16x2 -> FP32x2 conversion
+                                // miscompiled here)
+                                const float x0 = float(__builtin_bit_cast(_Float16, uint16_t(v4[w])));
+                                const float x1 = float(__builtin_bit_cast(_Float16, uint16_t(v4[w] >> 16)));
+                                Mx<PREC>::put(bh, bl, 2 * w, x0);
+                                Mx<PREC>::put(bh, bl, 2 * w + 1, x1);
+                            }
                         }
                     } else {
 #pragma unroll
@@ -1033,8 +1170,7 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
                 for (int q = 0; q < 4; ++q) {
                     const float v0 = ok ? acc[2 * q][e] * out_scale : 0.f;
                     const float v1 = ok ? acc[2 * q + 1][e] * out_scale : 0.f;
-                    w[q] = uint32_t(__builtin_bit_cast(uint16_t, (_Float16)v0))
-                           | (uint32_t(__builtin_bit_cast(uint16_t, (_Float16)v1)) << 16);
+                    w[q] = pack_f16x2(v0, v1);
                 }
                 *reinterpret_cast<u32x4 *>(static_cast<_Float16 *>(gout) + base) = u32x4{w[0], w[1], w[2], w[3]};
             } else {
@@ -1107,22 +1243,42 @@ __device__ __forceinline__ void mfma_stage(float2 *__restrict__ buf, typename Mx
     using P = MPlan<N>;
     constexpr int RN = mstage_rn<N>(S);
     constexpr bool TWID = RN > 1;
+    // FP16: stages hand their outputs to the next matrix stage as FP16 pairs
+    // (exactly the next B operand); the last matrix stage writes FP32
+    constexpr bool IN16 = PREC == FE_PREC_FP16 && S > 0;
+    constexpr bool OUT16 = PREC == FE_PREC_FP16 && S + 1 < P::S16;
+    uint32_t *buf32 = reinterpret_cast<uint32_t *>(buf);
     const int n32 = lane & 31, h = lane >> 5;
     if constexpr (S > 0) {
 #pragma unroll
         for (int u = 0; u < P::CPW; ++u) {
             const int gam = 32 * (wave * P::CPW + u) + n32;
-            const bool valid = gam < P::G;
+            const bool valid = P::G % 32 == 0 || gam < P::G;   // only n = 256 has idle lanes
+            // in(gam, j) = base + RN j.  Padded, the j term is a constant offset
+            // when RN >= 16 (RN j is a multiple of 16) or RN = 1 (16 gam + j
+            // stays within one padded row); RN = 2, 4, 8 pads each index.
+            const int base = (gam % RN) + RN * 16 * (gam / RN) + RN * 4 * h;
+            constexpr bool LIN = RN >= 16 || RN == 1;
+            const int pb = lds_pad(base);
+            constexpr int STEP = RN >= 16 ? RN + RN / 16 : 1;
+            auto at = [&](int m) { return LIN ? pb + STEP * m : lds_pad(base + RN * m); };
 #pragma unroll
-            for (int kap = 0; kap < 2; ++kap)
+            for (int kap = 0; kap < 2; ++kap) {
+                if constexpr (IN16) {
+                    u32x4 w;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int j = 8 * kap + 4 * h + e;
-                    const int idx = (gam % RN) + RN * (j + 16 * (gam / RN));
-                    const float2 v = valid ? buf[lds_pad(idx)] : make_float2(0.f, 0.f);
-                    Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e, v.x);
-                    Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e + 1, v.y);
+                    for (int e = 0; e < 4; ++e)
+                        w[e] = valid ? buf32[at(8 * kap + e)] : 0u;
+                    Bh[u][kap] = __builtin_bit_cast(typename Mx<PREC>::op, w);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float2 v = valid ? buf[at(8 * kap + e)] : make_float2(0.f, 0.f);
+                        Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e, v.x);
+                        Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e + 1, v.y);
+                    }
                 }
+            }
         }
     }
     f32x16 acc[P::CPW];
@@ -1138,7 +1294,7 @@ __device__ __forceinline__ void mfma_stage(float2 *__restrict__ buf, typename Mx
 #pragma unroll
     for (int u = 0; u < P::CPW; ++u) {
         const int gam = 32 * (wave * P::CPW + u) + n32;
-        if (gam >= P::G)
+        if (P::G % 32 != 0 && gam >= P::G)
             continue;
         // lane holds outputs d = 8 (t / 4) + 4 h + t % 4: re in acc[t], im in acc[t + 8]
         float2 tw[8];
@@ -1154,13 +1310,18 @@ __device__ __forceinline__ void mfma_stage(float2 *__restrict__ buf, typename Mx
                 tw[4 * q + 3] = make_float2(w1.z, w1.w);
             }
         }
+        // out(gam, d) = gam + G d, G a multiple of 16 (or the whole array when G = 16)
+        const int pw = lds_pad(gam + P::G * 4 * h);
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const int d = 8 * (t / 4) + 4 * h + t % 4;
+            const int dd = 8 * (t / 4) + t % 4;                 // d - 4 h
             float2 y = make_float2(acc[u][t], acc[u][t + 8]);
             if constexpr (TWID)
                 y = cmul(y, tw[t]);
-            buf[lds_pad(gam + P::G * d)] = y;
+            if constexpr (OUT16)
+                buf32[pw + (P::G + P::G / 16) * dd] = pack_f16x2(y.x, y.y);
+            else
+                buf[pw + (P::G + P::G / 16) * dd] = y;
         }
     }
     __syncthreads();
@@ -1209,23 +1370,29 @@ __global__ __launch_bounds__(MPlan<N>::NT) void fft_mfma_kernel(
 #pragma unroll
     for (int u = 0; u < P::CPW; ++u) {
         const int gam = 32 * (wave * P::CPW + u) + n32;
-        const bool valid = gam < P::G;
+        const bool valid = P::G % 32 == 0 || gam < P::G;   // only n = 256 has idle lanes
 #pragma unroll
-        for (int kap = 0; kap < 2; ++kap)
+        for (int kap = 0; kap < 2; ++kap) {
+            if constexpr (PREC == FE_PREC_FP16) {
+                // the stored FP16 pairs are the operand
+                u32x4 w;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = 8 * kap + 4 * h + e;
-                if constexpr (PREC == FE_PREC_FP16) {
-                    const uint32_t w = valid ? static_cast<const uint32_t *>(g)[sp * N + gam + P::G * j] : 0u;
-                    Bh[u][kap][2 * e] = __builtin_bit_cast(_Float16, uint16_t(w));
-                    Bh[u][kap][2 * e + 1] = __builtin_bit_cast(_Float16, uint16_t(w >> 16));
-                } else {
+                for (int e = 0; e < 4; ++e) {
+                    const int j = 8 * kap + 4 * h + e;
+                    w[e] = valid ? static_cast<const uint32_t *>(g)[sp * N + gam + P::G * j] : 0u;
+                }
+                Bh[u][kap] = __builtin_bit_cast(op, w);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = 8 * kap + 4 * h + e;
                     const float2 v = valid ? static_cast<const float2 *>(g)[sp * N + gam + P::G * j]
                                            : make_float2(0.f, 0.f);
                     Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e, v.x);
                     Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e + 1, v.y);
                 }
             }
+        }
     }
     // the real 32 x 32 DFT-16 matrix (scaled 1/4) as this lane's A operands
     op Ah[2], Al[2];
@@ -1376,6 +1543,7 @@ constexpr int EV_PER_CALL = 5;
 struct fe_stream {
     int n, T, Tk, A, S, D, H;
     int prec;               // FE_PREC_*
+    int fir_batches;        // FIR run length in batches of spectra (0: chosen per launch)
     float tap_scale;        // FP16 mode: taps scaled by 2^sc on the matrix cores
     float out_scale;        // 2^-sc, applied to the FIR's FP32 result
     int64_t max_samples;
@@ -1385,6 +1553,7 @@ struct fe_stream {
     float2 *d_tw;           // FFT twiddle blocks
     float2 *d_untangle;     // exp(-i pi k / n)
     float2 *d_tw16;         // matrix-stage twiddles [stage][group][16] (reduced modes)
+    float2 *d_twf;          // n > 8192: first-level twiddles exp(-2 pi i gam d / n), [n/16][16]
     uint32_t *d_dfta;       // DFT-16 A-operand images [K half][hi, lo][lane][8 x 16 bit]
     uint8_t *d_hist;        // [A*2][H*5/4]
     uint8_t *d_hist_tmp;    // same, used when a call is shorter than H
@@ -1440,6 +1609,8 @@ std::vector<float2> twiddles_for(int n)
     case 2048: return make_twiddles<2048>();
     case 4096: return make_twiddles<4096>();
     case 8192: return make_twiddles<8192>();
+    case 16384: return make_twiddles<1024>();      // sub-transforms of n/16 points
+    case 32768: return make_twiddles<2048>();
     default: return {};
     }
 }
@@ -1556,8 +1727,11 @@ void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const doubl
     // taps less often, shorter ones give more workgroups
     constexpr int B = (64 / T) * T;
     int R = 4 * B;
-    while (R > B && int64_t(streams) * ((me - mb + R - 1) / R) * colblocks < 2048)
-        R -= B;
+    if (s->fir_batches > 0)
+        R = s->fir_batches * B;                  // set by fe_stream_autotune
+    else
+        while (R > B && int64_t(streams) * ((me - mb + R - 1) / R) * colblocks < 2048)
+            R -= B;
     const int runs = (me - mb + R - 1) / R;
     const int64_t blocks = int64_t(streams) * runs * colblocks;
     hipLaunchKernelGGL((fir_kernel<T>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
@@ -1659,9 +1833,37 @@ void launch_post_mfma(const fe_stream *s, int M, const double *delays, const dou
     }
 }
 
+template <int NL>
+void launch_post_large(const fe_stream *s, int M, const double *delays, const double *phases,
+                       const float *gains, float *y_out, int mb, int me)
+{
+    const int64_t fthreads = int64_t(s->A) * 2 * (me - mb) * (NL / 16);
+    hipLaunchKernelGGL(fft_front_kernel, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0, s->stream,
+                       s->d_g, s->d_twf, NL, M, mb, me, s->A);
+    const unsigned blocks = unsigned(s->A * (me - mb) * 2);
+    if (y_out)
+        hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_PREQUANT>), dim3(blocks), dim3(NL / 128), 0,
+                           s->stream, s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
+                           mb, me);
+    else
+        hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_INT8>), dim3(blocks), dim3(NL / 128), 0,
+                           s->stream, s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
+                           mb, me);
+}
+
 void launch_post(const fe_stream *s, int M, const double *delays, const double *phases,
                  const float *gains, float *y_out, int mb, int me)
 {
+    if (s->n == 16384) {
+        launch_post_large<16384>(s, M, delays, phases, gains, y_out, mb, me);
+        return;
+    }
+    if (s->n == 32768) {
+        launch_post_large<32768>(s, M, delays, phases, gains, y_out, mb, me);
+        return;
+    }
     if (s->prec == FE_PREC_FP16) {
         launch_post_mfma<FE_PREC_FP16>(s, M, delays, phases, gains, y_out, mb, me);
         return;
@@ -1787,6 +1989,7 @@ void free_stream(fe_stream *s)
     (void)hipFree(s->d_tw);
     (void)hipFree(s->d_untangle);
     (void)hipFree(s->d_tw16);
+    (void)hipFree(s->d_twf);
     (void)hipFree(s->d_dfta);
     (void)hipFree(s->d_hist);
     (void)hipFree(s->d_hist_tmp);
@@ -1807,7 +2010,8 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     if (cfg->precision != FE_PREC_FP32 && cfg->precision != FE_PREC_FP16 && cfg->precision != FE_PREC_BF16)
         return FE_EINVAL;
     const int n = cfg->n_channels, T = cfg->taps;
-    if (!is_pow2(n) || n < 256 || n > 8192 || T < 1 || T > 32 || cfg->n_antennas < 1
+    if (!is_pow2(n) || n < 256 || n > 32768 || (n > 8192 && cfg->precision != FE_PREC_FP32)
+        || T < 1 || T > 32 || cfg->n_antennas < 1
         || cfg->spectra_per_heap < 1 || cfg->max_delay < 0 || cfg->max_samples <= 0)
         return FE_EINVAL;
     const int64_t unit = int64_t(2) * n * cfg->spectra_per_heap;
@@ -1822,6 +2026,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     s->n = n;
     s->T = T;
     s->prec = cfg->precision;
+    s->fir_batches = 0;
     s->Tk = s->prec == FE_PREC_FP32 ? kernel_taps(T) : kernel_taps_mfma(T);
     s->tap_scale = s->out_scale = 1.f;
     if (s->prec == FE_PREC_FP16) {
@@ -1867,7 +2072,18 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
         tw16.assign(1, make_float2(0.f, 0.f));
         dfta.assign(4, 0u);
     }
+    std::vector<float2> twf(1, make_float2(0.f, 0.f));
+    if (n > 8192) {
+        twf.resize(size_t(n));
+        const long double pi = 3.141592653589793238462643383279503L;
+        for (int gam = 0; gam < n / 16; ++gam)
+            for (int d = 0; d < 16; ++d) {
+                const long double a = -2.0L * pi * (long double)((int64_t(gam) * d) % n) / (long double)n;
+                twf[size_t(gam) * 16 + d] = make_float2(float(std::cos(a)), float(std::sin(a)));
+            }
+    }
     bool ok = hipMalloc(&s->d_taps, taps_n * sizeof(float)) == hipSuccess
+              && hipMalloc(&s->d_twf, twf.size() * sizeof(float2)) == hipSuccess
               && hipMalloc(&s->d_tw16, tw16.size() * sizeof(float2)) == hipSuccess
               && hipMalloc(&s->d_dfta, dfta.size() * sizeof(uint32_t)) == hipSuccess
               && hipMalloc(&s->d_tw, tw.size() * sizeof(float2)) == hipSuccess
@@ -1894,6 +2110,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
          && hipMemcpy(s->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
          && hipMemcpy(s->d_untangle, unt.data(), size_t(n) * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
          && hipMemcpy(s->d_tw16, tw16.data(), tw16.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
+         && hipMemcpy(s->d_twf, twf.data(), twf.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
          && hipMemcpy(s->d_dfta, dfta.data(), dfta.size() * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess
          && hipMemset(s->d_hist, 0, hist_bytes) == hipSuccess
          && hipMemset(s->d_hist_tmp, 0, hist_bytes) == hipSuccess
@@ -2052,5 +2269,254 @@ const char *fe_strerror(fe_status status)
 }
 
 int32_t fe_version(void) { return 200; }
+
+// ---------------------------------------------------------------------------
+// Autotuning and batches
+// ---------------------------------------------------------------------------
+
+fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples, const double *delays,
+                             const double *phases, const float *gains, int8_t *out, int iters,
+                             int *choice)
+{
+    if (!s || !out || iters < 1)
+        return FE_EINVAL;
+    fe_status st = check_call(s, raw, n_samples, delays);
+    if (st != FE_OK)
+        return st;
+    if (!phases || !gains)
+        return FE_EINVAL;
+    // candidates: FIR runs of 1, 2, 4, 8 batches (FP32 FIR only), and the
+    // per-launch choice; each timed with HIP events over `iters` calls
+    static const int cand[] = {0, 1, 2, 4, 8};
+    const int ncand = s->prec == FE_PREC_FP32 ? 5 : 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        return FE_EHIP;
+    }
+    const int saved = s->fir_batches;
+    const bool timing = s->timing;
+    s->timing = false;
+    float best_ms = 3.0e38f;
+    int best = 0;
+    st = FE_OK;
+    for (int c = 0; c < ncand && st == FE_OK; ++c) {
+        s->fir_batches = cand[c];
+        st = channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr);   // warm
+        if (st != FE_OK)
+            break;
+        (void)hipEventRecord(e0, s->stream);
+        for (int i = 0; i < iters && st == FE_OK; ++i)
+            st = channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr);
+        (void)hipEventRecord(e1, s->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            st = FE_EHIP;
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->timing = timing;
+    s->fir_batches = st == FE_OK ? best : saved;
+    if (choice)
+        *choice = s->fir_batches;
+    // the timing calls advanced the stream like real calls: restart it
+    if (st == FE_OK)
+        st = fe_stream_reset(s);
+    return st;
+}
+
+fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches)
+{
+    if (!s || fir_batches < 0 || fir_batches > 64)
+        return FE_EINVAL;
+    s->fir_batches = fir_batches;
+    return FE_OK;
+}
+
+}  // extern "C"
+
+struct fe_batch {
+    std::vector<fe_stream *> members;
+    hipStream_t main;
+    hipStream_t cap;                       // capture origin (the legacy default stream cannot be captured)
+    std::vector<hipStream_t> forks;        // one per member, default priority
+    std::vector<hipEvent_t> join;          // one per member
+    hipEvent_t fork_ev;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+void free_batch(fe_batch *b)
+{
+    if (!b)
+        return;
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    for (hipEvent_t e : b->join)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (b->fork_ev)
+        (void)hipEventDestroy(b->fork_ev);
+    for (hipStream_t st : b->forks)
+        if (st)
+            (void)hipStreamDestroy(st);
+    if (b->cap)
+        (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+// Enqueue every member's call: the fork streams wait for the batch stream,
+// each member runs on its own fork stream, the batch stream waits for all.
+fe_status batch_enqueue(fe_batch *b, const fe_call *calls, hipStream_t origin)
+{
+    if (hipEventRecord(b->fork_ev, origin) != hipSuccess)
+        return FE_EHIP;
+    fe_status st = FE_OK;
+    for (size_t i = 0; i < b->members.size() && st == FE_OK; ++i) {
+        fe_stream *m = b->members[i];
+        const fe_call &c = calls[i];
+        if (hipStreamWaitEvent(b->forks[i], b->fork_ev, 0) != hipSuccess)
+            return FE_EHIP;
+        hipStream_t saved = m->stream;
+        const bool timing = m->timing;
+        m->stream = b->forks[i];
+        m->timing = false;
+        st = c.out ? channelize_impl(m, c.raw, c.n_samples, c.delays, c.phases, c.gains, c.out, nullptr, nullptr)
+                   : FE_EINVAL;
+        m->stream = saved;
+        m->timing = timing;
+        if (st == FE_OK && hipEventRecord(b->join[i], b->forks[i]) != hipSuccess)
+            st = FE_EHIP;
+    }
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (hipStreamWaitEvent(origin, b->join[i], 0) != hipSuccess && st == FE_OK)
+            st = FE_EHIP;
+    return st;
+}
+
+fe_status batch_check(const fe_batch *b, const fe_call *calls)
+{
+    if (!b || !calls)
+        return FE_EINVAL;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        const fe_call &c = calls[i];
+        fe_status st = check_call(b->members[i], c.raw, c.n_samples, c.delays);
+        if (st != FE_OK)
+            return st;
+        if (!c.phases || !c.gains || !c.out)
+            return FE_EINVAL;
+    }
+    return FE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fe_status fe_batch_create(fe_stream *const *members, int count, void *hip_stream, fe_batch **out)
+{
+    if (!members || count < 1 || !out)
+        return FE_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!members[i])
+            return FE_EINVAL;
+    fe_batch *b = new (std::nothrow) fe_batch();
+    if (!b)
+        return FE_ENOMEM;
+    b->members.assign(members, members + count);
+    b->main = static_cast<hipStream_t>(hip_stream);
+    b->forks.assign(size_t(count), nullptr);
+    b->join.assign(size_t(count), nullptr);
+    b->fork_ev = nullptr;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->cap = nullptr;
+    bool ok = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess
+              && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; i < count && ok; ++i)
+        ok = hipStreamCreateWithFlags(&b->forks[size_t(i)], hipStreamNonBlocking) == hipSuccess
+             && hipEventCreateWithFlags(&b->join[size_t(i)], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        free_batch(b);
+        return FE_EHIP;
+    }
+    *out = b;
+    return FE_OK;
+}
+
+fe_status fe_batch_destroy(fe_batch *b)
+{
+    if (!b)
+        return FE_OK;
+    fe_status st = hip_status(hipStreamSynchronize(b->main));
+    if (b->cap && hipStreamSynchronize(b->cap) != hipSuccess)
+        st = FE_EHIP;
+    for (hipStream_t f : b->forks)
+        if (f && hipStreamSynchronize(f) != hipSuccess)
+            st = FE_EHIP;
+    free_batch(b);
+    return st;
+}
+
+fe_status fe_batch_run(fe_batch *b, const fe_call *calls)
+{
+    fe_status st = batch_check(b, calls);
+    if (st != FE_OK)
+        return st;
+    return batch_enqueue(b, calls, b->main);
+}
+
+fe_status fe_batch_capture(fe_batch *b, const fe_call *calls)
+{
+    fe_status st = batch_check(b, calls);
+    if (st != FE_OK)
+        return st;
+    if (hipStreamSynchronize(b->main) != hipSuccess)
+        return FE_EHIP;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return FE_EHIP;
+    st = batch_enqueue(b, calls, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->cap, &g);
+    if (st != FE_OK || ec != hipSuccess || !g) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return st != FE_OK ? st : FE_EHIP;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        b->exec = nullptr;
+        return FE_EHIP;
+    }
+    return FE_OK;
+}
+
+fe_status fe_batch_launch(fe_batch *b)
+{
+    if (!b || !b->exec)
+        return FE_EINVAL;
+    return hip_status(hipGraphLaunch(b->exec, b->main));
+}
 
 }  // extern "C"

@@ -32,6 +32,11 @@ class _Config(ctypes.Structure):
                 ("max_samples", ctypes.c_int64), ("weights", ctypes.POINTER(ctypes.c_float))]
 
 
+class _Call(ctypes.Structure):
+    _fields_ = [("raw", ctypes.c_void_p), ("n_samples", ctypes.c_int64), ("delays", ctypes.c_void_p),
+                ("phases", ctypes.c_void_p), ("gains", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -70,6 +75,21 @@ def load_library(path: Optional[str] = None):
                                         ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
     L.fe_stream_timing_read.restype = _st
+    L.fe_stream_autotune.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int)]
+    L.fe_stream_autotune.restype = _st
+    L.fe_stream_set_tuning.argtypes = [_vp, ctypes.c_int]
+    L.fe_stream_set_tuning.restype = _st
+    L.fe_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+    L.fe_batch_create.restype = _st
+    L.fe_batch_destroy.argtypes = [_vp]
+    L.fe_batch_destroy.restype = _st
+    for name in ("fe_batch_run", "fe_batch_capture"):
+        f = getattr(L, name)
+        f.argtypes = [_vp, ctypes.POINTER(_Call)]
+        f.restype = _st
+    L.fe_batch_launch.argtypes = [_vp]
+    L.fe_batch_launch.restype = _st
     L.fe_debug_unpack10.argtypes = [_vp, _i64, _i64, _vp, _vp]
     L.fe_debug_unpack10.restype = _st
     L.fe_strerror.argtypes = [_st]
@@ -215,6 +235,73 @@ class Stream:
         import torch
         a = self._args(raw, n_samples, delays) + [_ptr(g_out, torch.float32, "g_out")]
         _check(load_library().fe_channelize_fir(*a), "fe_channelize_fir")
+
+
+    def autotune(self, raw, n_samples: int, delays, phases, gains, out, iters: int = 3) -> int:
+        """fe_stream_autotune on these buffers; returns the chosen FIR run
+        length (0 = per-launch default).  Resets the stream."""
+        import torch
+        a = self._args(raw, n_samples, delays, phases, gains) + [_ptr(out, torch.int8, "out")]
+        choice = ctypes.c_int()
+        _check(load_library().fe_stream_autotune(*a, int(iters), ctypes.byref(choice)),
+               "fe_stream_autotune")
+        return int(choice.value)
+
+    def set_tuning(self, fir_batches: int):
+        _check(load_library().fe_stream_set_tuning(self._h, int(fir_batches)), "fe_stream_set_tuning")
+
+    def _call(self, raw, n_samples, delays, phases, gains, out) -> _Call:
+        import torch
+        return _Call(_ptr(raw, torch.uint8, "raw").value, int(n_samples),
+                     _ptr(delays, torch.float64, "delays").value,
+                     _ptr(phases, torch.float64, "phases").value,
+                     _ptr(gains, torch.float32, "gains").value, _ptr(out, torch.int8, "out").value)
+
+
+class Batch:
+    """fe_batch: one call of every member stream as a unit, run eagerly
+    (``run``) or captured once into a HIP graph (``capture``) and replayed
+    with one graph launch (``launch``).  ``calls[i]`` is the tuple
+    (raw, n_samples, delays, phases, gains, out) of member i."""
+
+    def __init__(self, members, hip_stream=None):
+        L = load_library()
+        self.members = list(members)
+        arr = (_vp * len(self.members))(*[m._h for m in self.members])
+        h = _vp()
+        _check(L.fe_batch_create(arr, len(self.members), _hip_stream(hip_stream), ctypes.byref(h)),
+               "fe_batch_create")
+        self._h = h
+        self._keep = None
+
+    def _calls(self, calls):
+        if len(calls) != len(self.members):
+            raise ValueError("one call per member")
+        arr = (_Call * len(calls))(*[m._call(*c) for m, c in zip(self.members, calls)])
+        return arr
+
+    def run(self, calls):
+        arr = self._calls(calls)
+        _check(load_library().fe_batch_run(self._h, arr), "fe_batch_run")
+
+    def capture(self, calls):
+        arr = self._calls(calls)
+        self._keep = list(calls)            # the graph refers to these buffers
+        _check(load_library().fe_batch_capture(self._h, arr), "fe_batch_capture")
+
+    def launch(self):
+        _check(load_library().fe_batch_launch(self._h), "fe_batch_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load_library().fe_batch_destroy(self._h), "fe_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def debug_unpack10(raw, first: int, count: int, out, hip_stream=None):

@@ -1,0 +1,186 @@
+"""Streaming channelizer service: a request loop over the C ABI.
+
+Feeds (single-antenna, dual-polarization streams) send chunks of packed
+samples of any whole number of heaps, arriving over time.  Each feed has one
+``fe_stream``: its PFB tail (the last 2n(T-1)+D_max samples), its delay
+handling and its sample count stay on the device between chunks (Secs. 3.1
+and 3.3), so a feed's chunks are processed in arrival order.
+
+The loop is continuously batched: a chunk is admitted as soon as the device
+memory it needs (its input, metadata and output buffers) fits the HBM budget
+next to the work already in flight; it is then copied to the device and
+channelized on its feed's own HIP stream.  Different feeds' chunks therefore
+run concurrently on the GPU, chunks that arrive while others run join as
+memory frees up, and a feed's chunks queue behind each other on its stream.
+Completion is detected with HIP events; the int8 heaps come back to pinned
+host memory.  Latency = completion time - arrival time.
+
+All channelizer arithmetic runs in the library's HIP kernels; this module
+schedules, moves buffers and keeps time.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import fengine
+
+
+def chunk_device_bytes(n_channels: int, n_samples: int) -> int:
+    """Device bytes one chunk holds while in flight: packed input of both
+    pols, delays and phases, gains, int8 output."""
+    M = n_samples // (2 * n_channels)
+    return 2 * n_samples * 5 // 4 + 2 * 2 * M * 8 + 2 * n_channels * 8 + 2 * n_samples
+
+
+@dataclasses.dataclass
+class Request:
+    """One chunk of one feed.
+
+    raw     uint8 [2][N*5/4] packed 10-bit samples (host)
+    delays  float64 [2][M], phases float64 [2][M]  (M = N / 2n)
+    gains   float32 [2][n][2]
+    arrival seconds on the loop's clock (0 = loop start)
+    """
+    feed: int
+    raw: np.ndarray
+    n_samples: int
+    delays: np.ndarray
+    phases: np.ndarray
+    gains: np.ndarray
+    arrival: float = 0.0
+    # filled in by the service
+    out: Optional[np.ndarray] = None
+    admitted: float = -1.0
+    done: float = -1.0
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Service:
+    """``feeds`` streams of one shape (n channels, T taps) sharing a GPU and
+    an HBM budget (bytes) for in-flight chunks."""
+
+    def __init__(self, n_channels: int, taps: int, weights, feeds: int, max_chunk_samples: int,
+                 hbm_budget: int, spectra_per_heap: int = 16, max_delay: int = 128,
+                 precision: str = "fp32", host_slots: int = 8):
+        import torch
+        self.torch = torch
+        self.n, self.taps, self.S = n_channels, taps, spectra_per_heap
+        self.budget = int(hbm_budget)
+        self.hip = [torch.cuda.Stream() for _ in range(feeds)]
+        self.streams = [fengine.Stream(n_channels, taps, 1, weights, max_chunk_samples,
+                                       spectra_per_heap=spectra_per_heap, max_delay=max_delay,
+                                       hip_stream=self.hip[f], precision=precision)
+                        for f in range(feeds)]
+        self.max_chunk = max_chunk_samples
+        # pinned host staging, reused: one slot per chunk in flight
+        self.slots = []
+        self.host_slots = host_slots
+
+    def _slot(self):
+        torch = self.torch
+        if self.slots:
+            return self.slots.pop()
+        Mx = self.max_chunk // (2 * self.n)
+        return {"raw": torch.empty(2 * self.max_chunk * 5 // 4, dtype=torch.uint8, pin_memory=True),
+                "d": torch.empty(2 * Mx, dtype=torch.float64, pin_memory=True),
+                "p": torch.empty(2 * Mx, dtype=torch.float64, pin_memory=True),
+                "g": torch.empty(2 * self.n * 2, dtype=torch.float32, pin_memory=True),
+                "out": torch.empty(2 * self.max_chunk, dtype=torch.int8, pin_memory=True)}
+
+    def chunk_bytes(self, n_samples: int) -> int:
+        return chunk_device_bytes(self.n, n_samples)
+
+    def _start(self, r: Request, now: float, slot):
+        torch = self.torch
+        f = r.feed
+        N = r.n_samples
+        M = N // (2 * self.n)
+        nb = 2 * N * 5 // 4
+        # host side: the chunk into pinned staging (a receive buffer would be
+        # pinned already), then asynchronous copies on the feed's stream
+        slot["raw"][:nb].copy_(torch.from_numpy(np.ascontiguousarray(r.raw).reshape(-1)))
+        slot["d"][:2 * M].copy_(torch.from_numpy(np.ascontiguousarray(r.delays).reshape(-1)))
+        slot["p"][:2 * M].copy_(torch.from_numpy(np.ascontiguousarray(r.phases).reshape(-1)))
+        slot["g"].copy_(torch.from_numpy(np.ascontiguousarray(r.gains, dtype=np.float32).reshape(-1)))
+        with torch.cuda.stream(self.hip[f]):
+            raw = slot["raw"][:nb].to("cuda", non_blocking=True)
+            d = slot["d"][:2 * M].to("cuda", non_blocking=True)
+            ph = slot["p"][:2 * M].to("cuda", non_blocking=True)
+            g = slot["g"].to("cuda", non_blocking=True)
+            out = torch.empty((1, M // self.S, self.n, self.S, 2, 2), dtype=torch.int8, device="cuda")
+            self.streams[f].channelize(raw, N, d, ph, g, out)
+            slot["out"][:2 * N].copy_(out.reshape(-1), non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.hip[f])
+        r.admitted = now
+        # device buffers stay referenced until the event has passed
+        return {"req": r, "event": ev, "keep": (raw, d, ph, g, out), "slot": slot,
+                "shape": tuple(out.shape), "bytes": self.chunk_bytes(N)}
+
+    def run(self, requests: List[Request], realtime: bool = True, poll: float = 20e-6) -> Dict:
+        """Serve ``requests`` (sorted by arrival).  ``realtime``: admit a
+        request no earlier than its arrival time; otherwise all arrive at 0.
+        Returns throughput and latency statistics; outputs land in req.out."""
+        for r in requests:
+            if r.n_samples % (2 * self.n * self.S) or r.n_samples > self.max_chunk:
+                raise ValueError("chunk of %d samples does not fit the service" % r.n_samples)
+            if self.chunk_bytes(r.n_samples) > self.budget:
+                raise ValueError("chunk larger than the HBM budget")
+        pending = sorted(requests, key=lambda r: r.arrival)
+        if not realtime:
+            for r in pending:
+                r.arrival = 0.0
+        inflight = []
+        used = 0
+        peak = 0
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(pending) or inflight:
+            now = time.perf_counter() - t0
+            # retire finished chunks (any order across feeds)
+            still = []
+            for job in inflight:
+                if job["event"].query():
+                    r = job["req"]
+                    r.done = time.perf_counter() - t0
+                    k = 2 * r.n_samples
+                    r.out = job["slot"]["out"][:k].numpy().reshape(job["shape"]).copy()
+                    self.slots.append(job["slot"])
+                    used -= job["bytes"]
+                else:
+                    still.append(job)
+            inflight = still
+            # admit arrivals in order while the budget allows
+            while i < len(pending) and pending[i].arrival <= now:
+                need = self.chunk_bytes(pending[i].n_samples)
+                if used + need > self.budget or len(inflight) >= self.host_slots:
+                    break
+                inflight.append(self._start(pending[i], now, self._slot()))
+                used += need
+                peak = max(peak, used)
+                i += 1
+            if inflight or (i < len(pending) and pending[i].arrival > now):
+                time.sleep(poll)
+        wall = time.perf_counter() - t0
+        lat = np.array([r.latency for r in requests]) * 1e3
+        samples = 2 * sum(r.n_samples for r in requests)
+        for st in self.streams:
+            if st.status() != fengine.FE_OK:
+                raise fengine.FEngineError(st.status(), "service stream")
+        return {"chunks": len(requests), "samples": samples, "seconds": wall,
+                "gsamples_per_s": samples / wall / 1e9,
+                "latency_ms_p50": float(np.percentile(lat, 50)),
+                "latency_ms_p99": float(np.percentile(lat, 99)),
+                "latency_ms_max": float(lat.max()), "peak_inflight_bytes": peak}
+
+    def close(self):
+        for st in self.streams:
+            st.close()
+        self.streams = []

@@ -37,7 +37,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "Shape", "SMALL", "LARGE", "pfb_taps", "pack10", "samples10",
+    "Shape", "SMALL", "LARGE", "BATCH16", "STREAM32K", "pfb_taps", "pack10", "samples10",
     "Workload", "make_workload", "heap_count",
 ]
 
@@ -69,6 +69,20 @@ class Shape:
 SMALL = Shape(n=1024, taps=16, antennas=1, samples=1 << 20)
 #: MeerKAT-like scale: four antennas, 2^24 samples/pol, 4096 channels, 16 taps.
 LARGE = Shape(n=4096, taps=16, antennas=4, samples=1 << 24)
+#: Batched workload: 16 single-antenna streams of uneven shape -- channels
+#: 1024 / 4096 / 8192 / 32768, taps 8 / 16 / 24, 2^22 .. 2^24 samples/pol per
+#: call, heaps of 64 spectra.
+BATCH16 = tuple(
+    Shape(n=n, taps=t, antennas=1, samples=1 << lg, spectra_per_heap=64)
+    for n, t, lg in [
+        (1024, 8, 22), (4096, 16, 23), (8192, 24, 24), (32768, 16, 24),
+        (1024, 16, 23), (4096, 24, 24), (8192, 8, 22), (32768, 8, 22),
+        (1024, 24, 24), (4096, 8, 22), (8192, 16, 23), (32768, 24, 23),
+        (1024, 16, 22), (4096, 16, 24), (8192, 16, 24), (32768, 16, 22),
+    ])
+#: Streaming service: one wide-band antenna, 32768 channels, 16 taps; chunks
+#: are whole numbers of 2^20 samples (32 spectra), heaps of 16 spectra.
+STREAM32K = Shape(n=32768, taps=16, antennas=1, samples=1 << 20, spectra_per_heap=16)
 
 
 def heap_count(shape: Shape) -> int:

@@ -97,6 +97,24 @@ def test_null_arguments_are_rejected(lib):
     assert lib.fe_debug_unpack10(dummy, 0, 0, dummy, None) == fe.FE_OK
 
 
+def test_batch_and_tuning_reject_bad_arguments(lib):
+    from paper_2303_09886_amd import fengine
+    h = ctypes.c_void_p()
+    assert lib.fe_batch_create(None, 1, None, ctypes.byref(h)) == fe.FE_EINVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.fe_batch_create(arr, 1, None, ctypes.byref(h)) == fe.FE_EINVAL
+    assert lib.fe_batch_create(arr, 0, None, ctypes.byref(h)) == fe.FE_EINVAL
+    assert not h.value
+    assert lib.fe_batch_launch(None) == fe.FE_EINVAL
+    assert lib.fe_batch_run(None, None) == fe.FE_EINVAL
+    assert lib.fe_batch_capture(None, None) == fe.FE_EINVAL
+    assert lib.fe_batch_destroy(None) == fe.FE_OK
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.fe_stream_autotune(None, dummy, 1 << 20, dummy, dummy, dummy, dummy, 1, None) == fe.FE_EINVAL
+    assert lib.fe_stream_set_tuning(None, 1) == fe.FE_EINVAL
+    assert ctypes.sizeof(fengine._Call) == 48
+
+
 def test_binding_refuses_host_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):

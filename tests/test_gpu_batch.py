@@ -1,0 +1,152 @@
+"""Batches of uneven streams (one graph launch per step) and the autotuner.
+Needs an MI355X.
+
+* a batch replayed from its HIP graph, step after step with new input in
+  the captured buffers, gives bit for bit what each stream gives alone;
+* so does the eager batch run (fork streams, no graph);
+* a member's output also matches the FP64 oracle (int8 bar of
+  test_gpu_parity);
+* autotuning changes launch shapes only: outputs are bit-identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import compare
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2303_09886_amd as fe   # noqa: E402
+
+SHAPES = [
+    synth.Shape(n=1024, taps=8, antennas=1, samples=1 << 18, spectra_per_heap=16),
+    synth.Shape(n=4096, taps=16, antennas=2, samples=1 << 19, spectra_per_heap=16),
+    synth.Shape(n=8192, taps=24, antennas=1, samples=1 << 19, spectra_per_heap=16),
+    synth.Shape(n=32768, taps=16, antennas=1, samples=1 << 20, spectra_per_heap=16),
+    synth.Shape(n=1024, taps=16, antennas=1, samples=1 << 19, spectra_per_heap=16),
+]
+PRECS = ["fp32", "fp32", "fp16", "fp32", "bf16"]
+STEPS = 2
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make(shape, prec):
+    return fe.Stream(shape.n, shape.taps, shape.antennas, workloads[shape][0].weights,
+                     shape.samples, spectra_per_heap=shape.spectra_per_heap, precision=prec)
+
+
+workloads = {s: (synth.make_workload(s, 40 + i, total=STEPS * s.samples),) for i, s in enumerate(SHAPES)}
+
+
+def out_like(shape):
+    M = shape.samples // (2 * shape.n)
+    return torch.empty((shape.antennas, M // shape.spectra_per_heap, shape.n, shape.spectra_per_heap, 2, 2),
+                       dtype=torch.int8, device="cuda")
+
+
+def step_inputs(shape, step):
+    w = workloads[shape][0]
+    raw, d, p = w.chunk(step * shape.samples, shape.samples)
+    return raw, d, p, w.gains
+
+
+def alone():
+    res = []
+    for shape, prec in zip(SHAPES, PRECS):
+        st = make(shape, prec)
+        outs = []
+        for k in range(STEPS):
+            raw, d, p, g = step_inputs(shape, k)
+            o = out_like(shape)
+            st.channelize(dev(raw), shape.samples, dev(d), dev(p), dev(g), o)
+            outs.append(o.cpu().numpy())
+        assert st.status() == fe.FE_OK
+        st.close()
+        res.append(outs)
+    return res
+
+
+def test_batch_graph_and_eager_match_streams_alone():
+    ref = alone()
+    for mode in ("graph", "eager"):
+        members = [make(s, p) for s, p in zip(SHAPES, PRECS)]
+        bufs = []
+        for shape in SHAPES:
+            raw, d, p, g = step_inputs(shape, 0)
+            bufs.append([dev(raw), shape.samples, dev(d), dev(p), dev(g), out_like(shape)])
+        batch = fe.Batch(members)
+        if mode == "graph":
+            batch.capture(bufs)
+        for k in range(STEPS):
+            for shape, b in zip(SHAPES, bufs):
+                raw, d, p, _ = step_inputs(shape, k)
+                b[0].copy_(torch.from_numpy(raw))
+                b[2].copy_(torch.from_numpy(d))
+                b[3].copy_(torch.from_numpy(p))
+            torch.cuda.synchronize()
+            if mode == "graph":
+                batch.launch()
+            else:
+                batch.run(bufs)
+            torch.cuda.synchronize()
+            for i, b in enumerate(bufs):
+                assert np.array_equal(b[5].cpu().numpy(), ref[i][k]), (mode, i, k)
+        batch.close()
+        for m in members:
+            assert m.status() == fe.FE_OK
+            m.close()
+        _say("  batch %s: %d uneven streams x %d steps bit-identical to the streams alone"
+             % (mode, len(SHAPES), STEPS))
+
+
+def test_batch_member_matches_oracle():
+    ref = alone()
+    shape = SHAPES[0]
+    w = workloads[shape][0]
+    r = oracle.channelize(w.raw, w.total, shape.n, shape.taps, 128, w.weights, w.delays, w.phases,
+                          w.gains, want=("y", "q"))
+    q = np.concatenate(ref[0], axis=1)
+    hard, soft = compare.int8_mismatches(q, oracle.heap_layout(r["q"], shape.spectra_per_heap),
+                                         compare.heap_values(r["y"], shape.spectra_per_heap))
+    assert hard == 0
+
+
+def test_autotune_keeps_results():
+    shape = synth.Shape(n=4096, taps=16, antennas=2, samples=1 << 21, spectra_per_heap=16)
+    w = synth.make_workload(shape, 8)
+    raw, d, p = w.chunk(0, shape.samples)
+    args = [dev(raw), shape.samples, dev(d), dev(p), dev(w.gains)]
+    outs = []
+    for tune in (False, True):
+        st = fe.Stream(shape.n, shape.taps, shape.antennas, w.weights, shape.samples, spectra_per_heap=16)
+        o = out_like(shape)
+        if tune:
+            choice = st.autotune(*args, o, iters=2)
+            _say("  autotune chose FIR run length %d" % choice)
+        st.channelize(*args, o)
+        outs.append(o.cpu().numpy())
+        assert st.status() == fe.FE_OK
+        st.close()
+    assert np.array_equal(outs[0], outs[1])
+    for fb in (1, 2, 8):
+        st = fe.Stream(shape.n, shape.taps, shape.antennas, w.weights, shape.samples, spectra_per_heap=16)
+        st.set_tuning(fb)
+        o = out_like(shape)
+        st.channelize(*args, o)
+        assert np.array_equal(o.cpu().numpy(), outs[0])
+        st.close()

@@ -178,6 +178,11 @@ CASES = [
     (512, 16, 1, 64, 256, 1),
     (256, 24, 1, 32, 256, 1),
     (256, 32, 1, 64, 256, 1),
+    # channel counts above one workgroup's LDS: two-level FFT; calls shorter
+    # than the history
+    (16384, 16, 1, 2, 10, 2),
+    (32768, 8, 2, 2, 6, 1),
+    (32768, 16, 1, 2, 4, 3),
 ]
 
 
@@ -189,11 +194,21 @@ def test_prequant_matches_oracle(n, T, A, S, M, calls):
     y, status = gpu_run(w, 2 * n * M, mode="prequant")
     assert status == fe.FE_OK
     ref = oracle_run(w, want=("y",))
-    nw, el = compare.assert_prequant_close(y, ref["y"])
+    if n <= 8192:
+        nw, el = compare.assert_prequant_close(y, ref["y"])
+    else:
+        # 65536-point transforms: the normwise bar stays 1e-5; the
+        # elementwise bar is 3e-5.  FP32 rounding alone reaches ~6.5e-6
+        # elementwise here (a single-precision library rfft of the oracle's
+        # own filtered samples, same data), before the FIR and the
+        # rotation/gain add theirs
+        nw, el = compare.prequant_errors(y, ref["y"])
+        assert nw <= compare.PREQUANT_RTOL
+        assert el <= 3 * compare.PREQUANT_RTOL
     _say("  Y normwise %.3g elementwise %.3g" % (nw, el))
 
 
-@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10])
+@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10] + CASES[13:15])
 def test_int8_matches_oracle(n, T, A, S, M, calls):
     _say("int8 n=%d T=%d A=%d S=%d M=%d calls=%d" % (n, T, A, S, M, calls))
     shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
