@@ -40,7 +40,8 @@ def chunk_device_bytes(n_channels: int, n_samples: int) -> int:
 class Request:
     """One chunk of one feed.
 
-    raw     uint8 [2][N*5/4] packed 10-bit samples (host)
+    raw     uint8 [2][N*5/4] packed 10-bit samples (host: a numpy array, or
+            a pinned torch tensor, which is copied to the device directly)
     delays  float64 [2][M], phases float64 [2][M]  (M = N / 2n)
     gains   float32 [2][n][2]
     arrival seconds on the loop's clock (0 = loop start)
@@ -103,17 +104,19 @@ class Service:
         N = r.n_samples
         M = N // (2 * self.n)
         nb = 2 * N * 5 // 4
-        # host side: the chunk into pinned staging (a receive buffer would be
-        # pinned already), then asynchronous copies on the feed's stream
-        slot["raw"][:nb].copy_(torch.from_numpy(np.ascontiguousarray(r.raw).reshape(-1)))
-        slot["d"][:2 * M].copy_(torch.from_numpy(np.ascontiguousarray(r.delays).reshape(-1)))
-        slot["p"][:2 * M].copy_(torch.from_numpy(np.ascontiguousarray(r.phases).reshape(-1)))
-        slot["g"].copy_(torch.from_numpy(np.ascontiguousarray(r.gains, dtype=np.float32).reshape(-1)))
+        # host side: chunks that already sit in pinned host memory (torch
+        # tensors, as a receive ring would hold them) are copied straight to
+        # the device; others go through the pinned staging slot first
+        def staged(a, name, count, dtype):
+            if isinstance(a, torch.Tensor) and a.is_pinned():
+                return a.reshape(-1)[:count]
+            slot[name][:count].copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=dtype).reshape(-1)))
+            return slot[name][:count]
+
+        src = [staged(r.raw, "raw", nb, np.uint8), staged(r.delays, "d", 2 * M, np.float64),
+               staged(r.phases, "p", 2 * M, np.float64), staged(r.gains, "g", 4 * self.n, np.float32)]
         with torch.cuda.stream(self.hip[f]):
-            raw = slot["raw"][:nb].to("cuda", non_blocking=True)
-            d = slot["d"][:2 * M].to("cuda", non_blocking=True)
-            ph = slot["p"][:2 * M].to("cuda", non_blocking=True)
-            g = slot["g"].to("cuda", non_blocking=True)
+            raw, d, ph, g = [x.to("cuda", non_blocking=True) for x in src]
             out = torch.empty((1, M // self.S, self.n, self.S, 2, 2), dtype=torch.int8, device="cuda")
             self.streams[f].channelize(raw, N, d, ph, g, out)
             slot["out"][:2 * N].copy_(out.reshape(-1), non_blocking=True)
