@@ -584,22 +584,51 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
                                               const float2 *__restrict__ gn, bool ok, int64_t sp, int tid,
                                               uint32_t *__restrict__ spec8, float2 *__restrict__ y_out)
 {
+    // channel k = k0 + S i with k0 = 2 tid + e: the padded LDS offsets of k
+    // and n - k, the coarse phase index and the table offsets all step by
+    // constants with i (S is a multiple of 16; of 64 from n = 512 up)
+    constexpr int S = 2 * NT;
+    constexpr int SP = S + S / 16;
+    int pk[2], pm[2];
+    float2 lo[2];
 #pragma unroll
-    for (int i = 0; i < N / 2 / NT; ++i) {
+    for (int e = 0; e < 2; ++e) {
+        const int k0 = 2 * tid + e;
+        pk[e] = lds_pad(k0);
+        pm[e] = lds_pad(N - k0);
+        if constexpr (S % 64 == 0)
+            lo[e] = ph_lo[k0 & 63];
+    }
+    // the per-channel constants (untangle twiddle, gain) come from L2: issue
+    // all of this thread's loads before the first use, so their latencies
+    // overlap instead of adding up channel by channel
+    constexpr int P = N / 2 / NT;
+    float4 wt[P], gt[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int j = tid + NT * i;
+        wt[i] = reinterpret_cast<const float4 *>(untangle)[j];
+        gt[i] = reinterpret_cast<const float4 *>(gn)[j];
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
         const int j = tid + NT * i;
         float2 Y[2];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
             const int k = 2 * j + e;
-            const int km = (N - k) & (N - 1);
-            const float2 zk = buf[lds_pad(k)];
-            const float2 zm = buf[lds_pad(km)];
+            const float2 zk = buf[pk[e] + SP * i];
+            // n - k, except k = 0, whose partner is itself
+            const float2 zm = buf[(i == 0 && k == 0) ? 0 : pm[e] - SP * i];
+            const float2 w = e == 0 ? make_float2(wt[i].x, wt[i].y) : make_float2(wt[i].z, wt[i].w);
+            const float2 gk = e == 0 ? make_float2(gt[i].x, gt[i].y) : make_float2(gt[i].z, gt[i].w);
             // 2E = Z[k] + conj Z[n-k], 2O = (Z[k] - conj Z[n-k]) / i, 2X = 2E + w 2O
             const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
             const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
-            const float2 X2 = cadd(E2, cmul(untangle[k], O2));       // w = exp(-i pi k / n)
-            const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);    // includes 1/2
-            Y[e] = ok ? cmul(gn[k], cmul(rot, X2)) : make_float2(0.f, 0.f);
+            const float2 X2 = cadd(E2, cmul(w, O2));                   // w = exp(-i pi k / n)
+            const float2 l = (S % 64 == 0) ? lo[e] : ph_lo[k & 63];
+            const float2 rot = cmul(ph_hi[k >> 6], l);                 // includes 1/2
+            Y[e] = ok ? cmul(gk, cmul(rot, X2)) : make_float2(0.f, 0.f);
         }
         if (MODE == OUT_PREQUANT) {
             reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
@@ -753,21 +782,33 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
         // one for dsel = 0, 8)
         const bool dup = half == 1 && (dd == 0 || dd == 8);
         if (!dup) {
-            for (int kk = tp; kk < NS; kk += NTS) {
-                const int k = dsel + 16 * kk;
-                const int km = (NL - k) & (NL - 1);
-                const int dm = km & 15, km2 = km >> 4;
-                const float2 zk = bh[lds_pad(kk)];
-                const float2 zm = buf[dm == dsel ? half : 1 - half][lds_pad(km2)];
-                const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
-                const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
-                const float2 X2 = cadd(E2, cmul(untangle[k], O2));
-                const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);
-                const float2 Y = ok ? cmul(gn[k], cmul(rot, X2)) : make_float2(0.f, 0.f);
-                if (MODE == OUT_PREQUANT)
-                    y_out[sp * NL + k] = Y;
-                else
-                    q16[k] = uint16_t(quant4(Y.x, Y.y, 0.f, 0.f));
+            // 8 channels at a time, their table loads issued together
+            for (int k8 = 0; k8 < NS / NTS; k8 += 8) {
+                float2 wk[8], gk[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int k = dsel + 16 * (tp + NTS * (k8 + r));
+                    wk[r] = untangle[k];
+                    gk[r] = gn[k];
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int kk = tp + NTS * (k8 + r);
+                    const int k = dsel + 16 * kk;
+                    const int km = (NL - k) & (NL - 1);
+                    const int dm = km & 15, km2 = km >> 4;
+                    const float2 zk = bh[lds_pad(kk)];
+                    const float2 zm = buf[dm == dsel ? half : 1 - half][lds_pad(km2)];
+                    const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
+                    const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
+                    const float2 X2 = cadd(E2, cmul(wk[r], O2));
+                    const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);
+                    const float2 Y = ok ? cmul(gk[r], cmul(rot, X2)) : make_float2(0.f, 0.f);
+                    if (MODE == OUT_PREQUANT)
+                        y_out[sp * NL + k] = Y;
+                    else
+                        q16[k] = uint16_t(quant4(Y.x, Y.y, 0.f, 0.f));
+                }
             }
         }
         __syncthreads();                                    // the buffers are refilled next round
@@ -1341,7 +1382,7 @@ __device__ __forceinline__ void mfma_stages(float2 *buf, typename Mx<PREC>::op (
 }
 
 template <int N, int PREC, int MODE>
-__global__ __launch_bounds__(MPlan<N>::NT) void fft_mfma_kernel(
+__global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_kernel(
     const void *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw16, const float2 *__restrict__ untangle,

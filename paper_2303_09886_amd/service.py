@@ -74,7 +74,12 @@ class Service:
         self.torch = torch
         self.n, self.taps, self.S = n_channels, taps, spectra_per_heap
         self.budget = int(hbm_budget)
+        # per feed: the compute stream (the feed's fe_stream), and copy
+        # streams in and out, so a chunk's transfers overlap its neighbours'
+        # kernels; all at default priority
         self.hip = [torch.cuda.Stream() for _ in range(feeds)]
+        self.h2d = [torch.cuda.Stream() for _ in range(feeds)]
+        self.d2h = [torch.cuda.Stream() for _ in range(feeds)]
         self.streams = [fengine.Stream(n_channels, taps, 1, weights, max_chunk_samples,
                                        spectra_per_heap=spectra_per_heap, max_delay=max_delay,
                                        hip_stream=self.hip[f], precision=precision)
@@ -115,13 +120,20 @@ class Service:
 
         src = [staged(r.raw, "raw", nb, np.uint8), staged(r.delays, "d", 2 * M, np.float64),
                staged(r.phases, "p", 2 * M, np.float64), staged(r.gains, "g", 4 * self.n, np.float32)]
-        with torch.cuda.stream(self.hip[f]):
+        with torch.cuda.stream(self.h2d[f]):
             raw, d, ph, g = [x.to("cuda", non_blocking=True) for x in src]
             out = torch.empty((1, M // self.S, self.n, self.S, 2, 2), dtype=torch.int8, device="cuda")
-            self.streams[f].channelize(raw, N, d, ph, g, out)
+            ev_in = torch.cuda.Event()
+            ev_in.record(self.h2d[f])
+        self.hip[f].wait_event(ev_in)
+        self.streams[f].channelize(raw, N, d, ph, g, out)         # enqueued on self.hip[f]
+        ev_k = torch.cuda.Event()
+        ev_k.record(self.hip[f])
+        self.d2h[f].wait_event(ev_k)
+        with torch.cuda.stream(self.d2h[f]):
             slot["out"][:2 * N].copy_(out.reshape(-1), non_blocking=True)
             ev = torch.cuda.Event()
-            ev.record(self.hip[f])
+            ev.record(self.d2h[f])
         r.admitted = now
         # device buffers stay referenced until the event has passed
         return {"req": r, "event": ev, "keep": (raw, d, ph, g, out), "slot": slot,
