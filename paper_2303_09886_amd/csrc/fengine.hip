@@ -122,21 +122,25 @@ __device__ __forceinline__ int xcd_logical(int b, int G)
 // ---------------------------------------------------------------------------
 // Kernel 1: unpack + coarse delay + FIR (Eq. (1)).
 //
-// Thread = one column t of one stream (antenna, pol) for a run of R <= 64
+// Thread = one column t of one stream (antenna, pol) for a run of R
 // consecutive spectra.  g_{F,t} = sum_j s[2n(F-T+1) - c_F + t + 2nj] h[t+2nj].
 // Viewed down column t, spectrum F reads rows F-T+1 .. F of the 2n-wide
 // sample matrix shifted by c_F, so consecutive spectra with equal c share
 // T-1 rows and each new spectrum needs one new sample.  Spectra go in groups
 // of T: the group's T new samples are loaded together (memory-level
-// parallelism), then its T outputs are formed from a 2T-1 register window.
-// Groups whose spectra all have the previous delay and read no history take
-// this fast path; anything else (a delay step, the history seam, the ragged
-// tail, an invalid delay) takes a general per-spectrum path.  The delay
-// split of spectrum m0+l is computed by lane l and broadcast with readlane,
-// so c is wave-uniform (SGPR) in the loop.
+// parallelism), one group ahead of their use, and its T outputs are formed
+// from a 2T-1 register window.  The workgroup first splits the delays of up
+// to FIR_SEG spectra into an LDS table (one per thread).  Each wave then
+// walks the spectra in spans of one delay (found with one table read per
+// lane and a ballot): a span's groups start at its first spectrum and its
+// last group is padded (the padding outputs are not stored), so a delay
+// step costs one refill of the T-1 older rows and part of one group.
+// Spectra with an invalid delay or rows before the call (the history seam)
+// take a general per-spectrum path.
 // ---------------------------------------------------------------------------
 
 constexpr int FIR_THREADS = 256;
+constexpr int FIR_SEG = 1024;              // spectra per delay table
 
 // Raw buffer descriptor (gfx9 family): base, no stride, `bytes` records;
 // loads outside [0, bytes) return zero, stores outside are dropped.  Used for
@@ -157,12 +161,13 @@ __device__ __forceinline__ void store_f32(float v, __amdgpu_buffer_rsrc_t r, uin
 }
 
 // Unaligned 16-bit global load (little-endian) at byte `off` of a
-// wave-uniform base (so the address is an SGPR pair plus one 32-bit VGPR).
-__device__ __forceinline__ uint32_t load_u16(const uint8_t *base, uint32_t off)
+// wave-uniform base in the global address space (so the address is an SGPR
+// pair plus one 32-bit VGPR).
+typedef const uint8_t __attribute__((address_space(1))) *gptr8;
+typedef uint16_t __attribute__((aligned(1))) u16_unaligned;
+__device__ __forceinline__ uint32_t load_u16(gptr8 base, uint32_t off)
 {
-    uint16_t u;
-    __builtin_memcpy(&u, base + off, 2);
-    return u;
+    return *reinterpret_cast<const u16_unaligned __attribute__((address_space(1))) *>(base + off);
 }
 
 // 10-bit sample from a little-endian 16-bit load u of the bytes holding it;
@@ -183,13 +188,16 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
     const float *__restrict__ taps, const double *__restrict__ delays,
     float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me)
 {
+    __shared__ int s_c[FIR_SEG];            // coarse delay of each spectrum of the segment, -1 if invalid
+
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int cb = lb % colblocks;
     const int rest = lb / colblocks;
     const int run = rest % runs;
     const int s = rest / runs;
-    const int t = cb * FIR_THREADS + threadIdx.x;
-    const int t_wave = __builtin_amdgcn_readfirstlane(cb * FIR_THREADS + (threadIdx.x & ~63));
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int t_blk = cb * FIR_THREADS;
+    const int t = t_blk + tid;
     const int m0 = mb + run * R;            // this launch covers spectra [mb, me)
     const int mend = min(m0 + R, me);
 
@@ -198,13 +206,7 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
     for (int j = 0; j < T; ++j)
         h[j] = taps[t + n2 * j];
 
-    // delays are split per batch of B spectra (lane l: spectrum b0 + l); the
-    // next batch's delays are loaded one batch ahead
-    constexpr int B = (64 / T) * T;
-    const int lane = threadIdx.x & 63;
     const double *ds = delays + int64_t(s) * M;
-    double d_next = (lane < B && m0 + lane < mend) ? ds[m0 + lane] : 0.0;
-
     const uint8_t *rs = raw + int64_t(s) * raw_stride;
     const uint8_t *hs = hist + int64_t(s) * hist_stride;
     float *gs = g + int64_t(s) * M * n2;
@@ -212,134 +214,158 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
     const int row_bytes = (n2 / 4) * 5;                       // 2n samples of 10 bits
     const uint32_t t_bytes = uint32_t(t) * 4u;
 
-    // X[i] holds the sample of row (g0 - T + 1 + i) at the current delay
-    float X[2 * T - 1];
+    // X: rows g0-T+1 .. g0-1 of column t at delay c_cur (raw 16-bit words
+    // straight after a refill); N: the raw words of rows g0 .. g0+T-1,
+    // loaded one group ahead of their use
+    float X[T - 1];
 #pragma unroll
-    for (int i = 0; i < 2 * T - 1; ++i)
+    for (int i = 0; i < T - 1; ++i)
         X[i] = 0.f;
-    int c_cur = -1;                                           // delay the window rows belong to
-    // outputs of the last fast group, stored only after the next group's
-    // loads are issued: loads and stores share one in-order wait counter, so
-    // storing first would make every group wait for the previous stores
-    // (the stores are unconditional so that the compiler's wait counts stay
-    // exact; with nothing pending the lane offset lies beyond the buffer's
-    // record count and the hardware drops the store)
+    int c_cur = -1;
+    uint32_t N[T];
+    auto issue = [&](int g0, int c, bool refill) {
+        // rows g0 .. g0+T-1 at delay c (rows past the call's last one, which
+        // only padded outputs use, read that last row): byte (5 i0)/4 of row
+        // pointers rs + r*row_bytes.  One running row pointer, kept a scalar
+        // operand by the empty asm: folded into the lane offset it would cost
+        // two VGPRs and two adds per row.
+        const uint32_t voff = uint32_t(5 * (n2 * g0 - c + t)) >> 2;
+        if (refill) {
+            const uint32_t v0 = voff - uint32_t((T - 1) * row_bytes);      // row g0-T+1, in the call
+            gptr8 rp = (gptr8)rs;
+#pragma unroll
+            for (int k = 0; k < T - 1; ++k) {
+                asm volatile("" : "+s"(rp));
+                X[k] = __builtin_bit_cast(float, load_u16(rp, v0));
+                rp += row_bytes;
+            }
+        }
+        gptr8 rp = (gptr8)rs;
+#pragma unroll
+        for (int r = 0; r < T; ++r) {
+            asm volatile("" : "+s"(rp));
+            N[r] = load_u16(rp, voff);
+            if (g0 + r + 1 < M)
+                rp += row_bytes;
+        }
+    };
+
+    // outputs of the last group, stored right after the next loads are
+    // issued (loads and stores share one in-order wait counter; the stores
+    // are unconditional so that the compiler's wait counts stay the same on
+    // every path).  Outputs r >= pend_cnt are padding: their scalar offset
+    // DROP puts them beyond the buffer's record count and the hardware drops
+    // them.
     constexpr uint32_t DROP = 0x80000000u;
     float pend[T];
 #pragma unroll
     for (int r = 0; r < T; ++r)
         pend[r] = 0.f;
-    uint32_t pend_voff = DROP, pend_soff = 0;
+    int pend_cnt = 0;
+    uint32_t pend_soff = 0;
     auto flush = [&]() {
 #pragma unroll
         for (int r = 0; r < T; ++r)
-            store_f32(pend[r], rg, pend_voff, pend_soff + uint32_t(r * n2 * 4));
-        pend_voff = DROP;
+            store_f32(pend[r], rg, t_bytes, r < pend_cnt ? pend_soff + uint32_t(r * n2 * 4) : DROP);
+        pend_cnt = 0;
     };
 
-    for (int b0 = m0; b0 < mend; b0 += B) {
-    const int bend = min(b0 + B, mend);
-    int c_lane = 0, ok_lane = 0;
-    if (lane < B && b0 + lane < bend) {
-        double tau;
-        ok_lane = split_delay(d_next, D, c_lane, tau) ? 1 : 0;
-    }
-    d_next = (lane < B && bend + lane < mend) ? ds[bend + lane] : 0.0;
-
-    for (int g0 = b0; g0 < bend; g0 += T) {
-        // fast path: the whole group has one delay cg and reads no history;
-        // if cg differs from the delay of the window rows held in X, the
-        // T-1 older rows are reloaded together with the T new ones
-        const int cg = __builtin_amdgcn_readlane(c_lane, g0 - b0);
-        bool fast = g0 + T <= bend;
-        if (fast) {
-#pragma unroll
-            for (int r = 1; r < T; ++r)
-                fast = fast && __builtin_amdgcn_readlane(c_lane, g0 - b0 + r) == cg;
+    for (int sa = m0; sa < mend; sa += FIR_SEG) {
+        const int se = min(sa + FIR_SEG, mend);
+        // delay split of the segment's spectra, one per thread
+        __syncthreads();                                      // the last segment's table is read
+        for (int i = tid; i < se - sa; i += FIR_THREADS) {
+            int c;
+            double tau;
+            s_c[i] = split_delay(ds[sa + i], D, c, tau) ? c : -1;
         }
-        const bool refill = cg != c_cur;
-        fast = fast && int64_t(n2) * (refill ? g0 - T + 1 : g0) - cg + t_wave >= 0;
-        if (fast) {
-            // rows g0 .. g0+T-1 of column t at delay cg: byte offsets
-            // (5 i0)/4 + r*row_bytes, same bit phase in every row
-            const int i0 = n2 * g0 - cg + t;
-            const uint32_t lo = 6u - ((uint32_t(i0) & 3u) << 1);
-            const uint32_t voff = uint32_t(5 * i0) >> 2;
-            // all loads first (raw 16-bit words parked in the window slots they
-            // will occupy), then the conversions
-            if (refill) {
+        __syncthreads();
+
+        int m = sa;
+        while (m < se) {
+            const int c = __builtin_amdgcn_readfirstlane(s_c[m - sa]);
+            if (c < 0 || int64_t(n2) * (m - T + 1) - c + t_blk < 0) {
+                // general path for spectrum m (an invalid delay, or rows
+                // before the call): all T rows loaded, invalid delays read at
+                // delay 0 and output zeros
+                flush();
+                int i = n2 * (m - T + 1) - max(c, 0) + t;      // sample of row m-T+1
+                float acc = 0.f;
 #pragma unroll
-                for (int k = 1; k < T; ++k)       // rows g0-k
-                    X[T - 1 - k] = __builtin_bit_cast(float, load_u16(rs, voff - uint32_t(k * row_bytes)));
-                c_cur = cg;
+                for (int j = 0; j < T; ++j) {
+                    // (a lane value stepped row by row: hoisted, the T row
+                    // offsets would each hold scalar registers)
+                    asm volatile("" : "+v"(i));
+                    acc = fmaf(float(sample_at(rs, hs, i, H)), h[j], acc);
+                    i += n2;
+                }
+                store_f32(c >= 0 ? acc : 0.f, rg, t_bytes, uint32_t(m * n2 * 4));
+                c_cur = -1;                                   // X holds no rows
+                ++m;
+                continue;
             }
-#pragma unroll
-            for (int r = 0; r < T; ++r)
-                X[T - 1 + r] = __builtin_bit_cast(float, load_u16(rs, voff + uint32_t(r * row_bytes)));
-            __builtin_amdgcn_sched_barrier(0);    // keep the stores behind the loads
+            // span of spectra from m with this delay: 64 table entries at a
+            // time, one per lane
+            int send = m;
+            for (;;) {
+                const int ix = send - sa + lane;
+                const int v = ix < se - sa ? s_c[ix] : -2;
+                const uint64_t other = ~__builtin_amdgcn_ballot_w64(v == c);
+                if (other) {
+                    send += int(__builtin_ctzll(other));
+                    break;
+                }
+                send += 64;
+            }
+            // its groups g0 = m, m+T, ..., the last one padded: the first
+            // group's rows (and, unless they continue the held window, its
+            // T-1 older rows), then each group's new rows one group ahead
+            const bool refill = c != c_cur;
+            issue(m, c, refill);
             flush();
+            const uint32_t lo = 6u - ((uint32_t(t - c) & 3u) << 1);    // bit phase of every sample
             if (refill) {
 #pragma unroll
-                for (int i = 0; i + 1 < T; ++i)
+                for (int i = 0; i < T - 1; ++i)
                     X[i] = field10(__builtin_bit_cast(uint32_t, X[i]), lo);
             }
+            for (int g0 = m;; g0 += T) {
+                float Y[T];
 #pragma unroll
-            for (int r = 0; r < T; ++r)
-                X[T - 1 + r] = field10(__builtin_bit_cast(uint32_t, X[T - 1 + r]), lo);
+                for (int r = 0; r < T; ++r)
+                    Y[r] = field10(N[r], lo);
+                const bool ahead = g0 + T < send;
+                // unconditional, so that the loaded registers are the same on
+                // every path (a conditional load makes the compiler copy them,
+                // waiting for the loads); after the span's last group its rows
+                // are read again and not used
+                issue(ahead ? g0 + T : g0, c, false);
+                // the last group's stores go behind the loads, on every path T
+                // of them: the wait for the loads then counts exactly T later
+                // operations
+                flush();
+                __builtin_amdgcn_sched_barrier(0);            // keep the memory operations ahead of the arithmetic
 #pragma unroll
-            for (int r = 0; r < T; ++r) {
-                float acc = 0.f;
-#pragma unroll
-                for (int j = 0; j < T; ++j)
-                    acc = fmaf(X[r + j], h[j], acc);
-                const int ok = __builtin_amdgcn_readlane(ok_lane, g0 - b0 + r);
-                pend[r] = ok ? acc : 0.f;
-            }
-            pend_voff = t_bytes;
-            pend_soff = uint32_t(g0 * n2 * 4);
-        } else {
-            flush();
-            // general path, one spectrum at a time with a shifting window W of
-            // rows m-T+1 .. m; starts from the fast path's rows when the delay
-            // still matches, reloads all T rows when the delay changes.
-            float W[T];
-#pragma unroll
-            for (int j = 0; j + 1 < T; ++j)
-                W[j + 1] = X[j];                      // rows g0-T+1 .. g0-1 -> W[1 .. T-1]
-            int cw = c_cur;
-#pragma unroll 1
-            for (int m = g0; m < min(g0 + T, bend); ++m) {
-                const int c = __builtin_amdgcn_readlane(c_lane, m - b0);
-                const int64_t base = int64_t(n2) * (m - T + 1) - c + t;   // row m-T+1
-                if (c != cw) {
+                for (int r = 0; r < T; ++r) {
+                    float acc = 0.f;
 #pragma unroll
                     for (int j = 0; j < T; ++j)
-                        W[j] = float(sample_at(rs, hs, base + int64_t(n2) * j, H));
-                    cw = c;
-                } else {
-#pragma unroll
-                    for (int j = 0; j + 1 < T; ++j)
-                        W[j] = W[j + 1];
-                    W[T - 1] = float(sample_at(rs, hs, base + int64_t(n2) * (T - 1), H));
+                        acc = fmaf(j + r < T - 1 ? X[j + r] : Y[j + r - (T - 1)], h[j], acc);
+                    pend[r] = acc;
                 }
-                float acc = 0.f;
+                pend_cnt = min(T, send - g0);
+                pend_soff = uint32_t(g0 * n2 * 4);
+                // rows g0+1 .. g0+T-1 become the older rows of the next group
 #pragma unroll
-                for (int j = 0; j < T; ++j)
-                    acc = fmaf(W[j], h[j], acc);
-                const int ok = __builtin_amdgcn_readlane(ok_lane, m - b0);
-                store_f32(ok ? acc : 0.f, rg, t_bytes, uint32_t(m * n2 * 4));
+                for (int i = 0; i < T - 1; ++i)
+                    X[i] = Y[i + 1];
+                if (!ahead)
+                    break;
             }
-            // hand the window back: rows g0+1 .. g0+T-1 (meaningful only if the group was whole)
-#pragma unroll
-            for (int j = 0; j + 1 < T; ++j)
-                X[T + j] = W[j + 1];
-            c_cur = cw;
+            // a padded last group leaves rows past the span in X
+            c_cur = (send - m) % T == 0 ? c : -1;
+            m = send;
         }
-        // rows g0+1 .. g0+T-1 become the first T-1 rows of the next group
-#pragma unroll
-        for (int i = 0; i < T - 1; ++i)
-            X[i] = X[i + T];
-    }
     }
     flush();
 }

@@ -6,7 +6,8 @@ Needs an MI355X.
 * so does the eager batch run (fork streams, no graph);
 * a member's output also matches the FP64 oracle (int8 bar of
   test_gpu_parity);
-* autotuning changes launch shapes only: outputs are bit-identical.
+* autotuning changes launch shapes only: outputs are bit-identical, also
+  for FIR runs longer than the FIR's per-workgroup delay table.
 """
 import sys
 
@@ -150,3 +151,32 @@ def test_autotune_keeps_results():
         st.channelize(*args, o)
         assert np.array_equal(o.cpu().numpy(), outs[0])
         st.close()
+
+
+def test_fir_runs_longer_than_the_delay_table():
+    """FIR run lengths of 64 .. 4096 spectra over 2048 spectra whose coarse
+    delay steps every ~100 spectra: runs cross the 1024-spectrum segments of
+    the FIR's delay table, some with a delay that continues across the seam.
+    Each output is formed by the same arithmetic whatever the run length, so
+    the results are bit-identical, and they match the oracle."""
+    shape = synth.Shape(n=256, taps=16, antennas=1, samples=1 << 20, spectra_per_heap=16)
+    w = synth.make_workload(shape, 9, delay_rate=1e-4)
+    raw, d, p = w.chunk(0, shape.samples)
+    args = [dev(raw), shape.samples, dev(d), dev(p), dev(w.gains)]
+    outs = []
+    for fb in (0, 1, 16, 64):
+        _say("  FIR run length %d batches" % fb)
+        st = fe.Stream(shape.n, shape.taps, shape.antennas, w.weights, shape.samples, spectra_per_heap=16)
+        st.set_tuning(fb)
+        o = out_like(shape)
+        st.channelize(*args, o)
+        assert st.status() == fe.FE_OK
+        outs.append(o.cpu().numpy())
+        st.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    r = oracle.channelize(w.raw, w.total, shape.n, shape.taps, 128, w.weights, w.delays, w.phases,
+                          w.gains, want=("y", "q"))
+    hard, soft = compare.int8_mismatches(outs[0], oracle.heap_layout(r["q"], 16),
+                                         compare.heap_values(r["y"], 16))
+    assert hard == 0
