@@ -27,6 +27,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -942,6 +943,9 @@ __device__ __forceinline__ f32x4 mma16(const typename Mx<PREC>::op &ah, const ty
 // the staging area reads its operands directly from memory instead.
 // ---------------------------------------------------------------------------
 
+// two dwords at a 4-byte aligned address (one 8-byte load)
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
 constexpr int FM_COLS = 64;                // columns per tile
 constexpr int FM_SPEC = 256;               // spectra per tile (16 blocks)
 constexpr int FM_WMAX = 92;                // staged columns (23 groups of 4): 64 + delay spread + 3
@@ -961,11 +965,13 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, float tap_scale, float out_scale,
     const double *__restrict__ delays, void *__restrict__ gout,
-    int n2, int M, int D, int mb, int me, int ctiles, int ftiles)
+    int n2, int M, int D, int mb, int me, int ctiles, int ftiles, int chain)
 {
     using P = FirM<TK>;
     typedef typename Mx<PREC>::op op;
     constexpr int NPART = Mx<PREC>::split ? 2 : 1;          // tap parts (hi, lo)
+    constexpr int PRS = P::ROWS / 2;                         // staged row pairs
+    constexpr int IT = (PRS + 7) / 8;                        // row pairs per staging thread
     __shared__ uint32_t stage[FM_WMAX * P::RPW];             // [u][row pair] FP16 x 2
     // tap vectors, 16-bit, [part][col][v]; built first in the staging area
     uint16_t (*zt)[FM_COLS][P::ZL] = reinterpret_cast<uint16_t (*)[FM_COLS][P::ZL]>(stage);
@@ -973,102 +979,373 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
     // the same as overlapping pairs: zd[part][col][v] = (z[v], z[v + 1]), so
     // that 8 consecutive taps from any offset are 4 aligned dwords
     __shared__ uint32_t zd[NPART][FM_COLS][P::ZL];
-    __shared__ int cdel[FM_SPEC];                            // coarse delay, -1 if invalid
-    __shared__ uint8_t pass_of[FM_SPEC];
-    __shared__ int pdel[16][16];                             // [block][pass] delay
-    __shared__ int red[3];                                   // cmin, cmax, passes
+    // delay analysis of two tiles at a time (buffer = tile index parity)
+    __shared__ int cdel[2][FM_SPEC];                         // coarse delay, -1 if invalid
+    __shared__ uint8_t pass_of[2][FM_SPEC];
+    __shared__ int pdel[2][16][16];                          // [block][pass] delay
+    __shared__ int wred[2][4][3];                            // per wave: min, max delay, passes
 
     const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int ct = lb % ctiles;
     const int rest = lb / ctiles;
-    const int ft = rest % ftiles;
-    const int s = rest / ftiles;
+    const int nch = (ftiles + chain - 1) / chain;
+    const int ch = rest % nch;
+    const int s = rest / nch;
     const int t0 = ct * FM_COLS;
-    const int F0 = mb + ft * FM_SPEC;
+    const int fb = ch * chain, fe = min(fb + chain, ftiles);  // this workgroup's spectrum tiles
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint8_t *rs = raw + int64_t(s) * raw_stride;
     const uint8_t *hs = hist + int64_t(s) * hist_stride;
+    const double *ds = delays + int64_t(s) * M;
 
-    // ---- delays of the tile's spectra
-    if (tid == 0) {
-        red[0] = 0x7fffffff;
-        red[1] = -1;
-        red[2] = 1;
-    }
-    {
-        const int F = F0 + tid;
+    // ---- tile analysis.  split: one spectrum per thread, wave extremes of the
+    // valid delays.  passes (after a barrier): blocks of 16 spectra run one
+    // pass per stretch of equal delay; invalid spectra count as the tile's
+    // smallest delay (any staged delay: their outputs are zeroed).
+    auto load_delay = [&](int f) -> double {
+        const int F = mb + f * FM_SPEC + tid;
+        return F < me ? ds[F] : 0.0;
+    };
+    auto split_tile = [&](int f, double d) {
+        const int F = mb + f * FM_SPEC + tid;
         int c = -1;
         if (F < me) {
             int cc;
             double tau;
-            if (split_delay(delays[int64_t(s) * M + F], D, cc, tau))
+            if (split_delay(d, D, cc, tau))
                 c = cc;
         }
-        cdel[tid] = c;
-    }
-    // ---- tap vectors: zt[col][16 + j] = h'[t + 2n j] (scaled), zero elsewhere;
-    // lanes take consecutive columns (coalesced), all loads issued first
+        cdel[f & 1][tid] = c;
+        int mn = c >= 0 ? c : 0x7fffffff, mx = c;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = min(mn, __shfl_xor(mn, o));
+            mx = max(mx, __shfl_xor(mx, o));
+        }
+        if (lane == 0) {
+            wred[f & 1][wave][0] = mn;
+            wred[f & 1][wave][1] = mx;
+        }
+    };
+    auto tile_range = [&](int f, int &cmin, int &cmax) {
+        const int b = f & 1;
+        // (the same in every lane: made scalar so that what depends on it stays scalar)
+        cmin = __builtin_amdgcn_readfirstlane(min(min(wred[b][0][0], wred[b][1][0]), min(wred[b][2][0], wred[b][3][0])));
+        cmax = __builtin_amdgcn_readfirstlane(max(max(wred[b][0][1], wred[b][1][1]), max(wred[b][2][1], wred[b][3][1])));
+        if (cmax < 0)
+            cmin = cmax = 0;                                 // no valid spectrum
+    };
+    auto passes = [&](int f) {
+        const int b = f & 1;
+        int cmin, cmax;
+        tile_range(f, cmin, cmax);
+        const int c0 = cdel[b][tid];
+        const int ce = c0 >= 0 ? c0 : cmin;
+        const int cp = __shfl_up(ce, 1);
+        const int j = lane & 15;                             // spectrum within its block
+        const bool chg = j != 0 && ce != cp;
+        const uint64_t bits = (__builtin_amdgcn_ballot_w64(chg) >> (lane & ~15)) & 0xffffull;
+        const int p = __builtin_popcountll(bits & ((2ull << j) - 1));
+        pass_of[b][tid] = uint8_t(p);
+        const int blk = tid >> 4;
+        if (j == 0 || chg)
+            pdel[b][blk][p] = ce;
+        const int nb = __builtin_popcountll(bits) + 1;
+        if (j == 15)
+            for (int q = nb; q < 16; ++q)
+                pdel[b][blk][q] = ce;                        // fewer passes than the tile's most: repeat the last
+        const int mx = max(max(__builtin_amdgcn_readlane(nb, 15), __builtin_amdgcn_readlane(nb, 31)),
+                           max(__builtin_amdgcn_readlane(nb, 47), __builtin_amdgcn_readlane(nb, 63)));
+        if (lane == 0)
+            wred[b][wave][2] = mx;
+    };
+    // staged columns start on a 4-sample group (5 whole bytes): staged column
+    // u holds sample 2n r + 4 gq0 + u of row r, gq0 = floor((t0 - cmax) / 4)
+    struct Geo {
+        int cmin, cmax, gq0, u0, ngr;
+        bool staged;
+    };
+    auto geometry = [&](int f) {
+        Geo G;
+        tile_range(f, G.cmin, G.cmax);
+        G.gq0 = (t0 - G.cmax) >> 2;                          // arithmetic shift = floor
+        G.u0 = (t0 - G.cmax) - 4 * G.gq0;                    // 0 .. 3
+        G.ngr = (FM_COLS + G.cmax - G.cmin + G.u0 + 3) >> 2; // groups per staged row
+        G.staged = 4 * G.ngr <= FM_WMAX;
+        return G;
+    };
+
+    // ---- staging of rows [row0, row0 + ROWS) of tile f as FP16 row pairs.
+    // Thread (q = tid % 32, prs = tid / 32) takes group q (4 samples in 5
+    // bytes) of row pairs prs, prs + 8, ...: each group read as two aligned
+    // dwords (in range: every chunk and history row is a multiple of 4
+    // bytes).  The loads go to registers first (they are issued a tile ahead,
+    // before the previous tile's contraction), the conversion to LDS later.
+    const int q = tid & 31, prs = tid >> 5;
+    const int gpr = n2 >> 2;                                 // groups per row
+    const int hist_g = H >> 2;
+    const int ncall_g = int(Ncall >> 2);
+    auto group_of = [&](int f, const Geo &G, int pr, int h2) {
+        const int row0 = mb + f * FM_SPEC - TK + 1;          // call-relative row of staged row 0
+        return gpr * (row0 + 2 * pr + h2) + G.gq0 + q;
+    };
+    uint32_t dw[IT][2][2];
+    const int row_bytes = 5 * gpr;                           // multiple of 4
+    // interior tile: every group the staging lanes read lies in the call, so
+    // the words are read without per-load checks at a scalar row pointer plus
+    // one lane offset (the rows of lane pair prs are 2 prs below the
+    // pointer; a group's byte phase is the same in every row)
+    auto interior = [&](int f, const Geo &G) {
+        const int row0 = mb + f * FM_SPEC - TK + 1;
+        return G.staged && row0 >= 1 && gpr * (row0 + P::ROWS - 1) + G.gq0 + 31 < ncall_g;
+    };
+    auto stage_load = [&](int f) {
+        const Geo G = geometry(f);
+        if (interior(f, G)) {
+            const int row0 = mb + f * FM_SPEC - TK + 1;
+            // a group's first byte is 5 (gq0 + q) from its row's start, which
+            // is negative for groups before column 0 (gq0 < 0): the pointer
+            // starts a row early so that the unsigned lane offset stays
+            // positive (the dword index is floored: arithmetic shift)
+            const uint32_t lane_off =
+                uint32_t((2 * prs + 1) * row_bytes + 4 * ((5 * (G.gq0 + q)) >> 2));
+            gptr8 rp = (gptr8)rs + int64_t(row0 - 1) * row_bytes;
+#pragma unroll
+            for (int k = 0; k < IT; ++k) {
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) {
+                    const u32x2_a4 w = *reinterpret_cast<const u32x2_a4 __attribute__((address_space(1))) *>(rp + lane_off);
+                    dw[k][h2][0] = w[0];
+                    dw[k][h2][1] = w[1];
+                    rp += h2 == 0 ? row_bytes : 15 * row_bytes;   // rows +1, then on to the next 16
+                }
+            }
+            return;
+        }
+        if (!G.staged || q >= G.ngr)
+            return;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int pr = prs + 8 * k;
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const int ga = group_of(f, G, pr, h2);
+                const bool in_hist = ga < 0;
+                const bool ok = ga < ncall_g;
+                const int byte = 5 * (in_hist ? ga + hist_g : ga);
+                const uint8_t *base = in_hist ? hs : rs;
+                // unconditional loads (offset 0 stands in for rows outside
+                // the call; their words are zeroed at the conversion: a
+                // select here would wait for each load in turn)
+                const uint32_t *p32 = reinterpret_cast<const uint32_t *>(base) + (ok ? byte >> 2 : 0);
+                dw[k][h2][0] = p32[0];
+                dw[k][h2][1] = p32[1];
+            }
+        }
+    };
+    auto stage_write = [&](int f) {
+        const Geo G = geometry(f);
+        if (!G.staged || q >= G.ngr)
+            return;
+        const bool inner = interior(f, G);
+        // in an interior tile every group has the byte phase of row 0
+        const uint32_t o_in = uint32_t(5 * (G.gq0 + q)) & 3u;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int pr = prs + 8 * k;
+            float x[2][4];
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                uint32_t o = o_in, w0 = dw[k][h2][0], w1 = dw[k][h2][1];
+                if (!inner) {
+                    const int ga = group_of(f, G, pr, h2);
+                    o = uint32_t(5 * (ga < 0 ? ga + hist_g : ga)) & 3u;
+                    if (ga >= ncall_g)
+                        w0 = w1 = 0u;                                // rows past the call
+                }
+                // big-endian bytes b0..b3 and (b3, b4) of the group
+                const uint32_t be0 = __builtin_amdgcn_perm(w1, w0, 0x00010203u + 0x01010101u * o);
+                const uint32_t be1 = __builtin_amdgcn_perm(w1, w0, 0x0C0C0000u | ((o + 3u) << 8) | (o + 4u));
+                x[h2][0] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 22u, 10u)));
+                x[h2][1] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 12u, 10u)));
+                x[h2][2] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 2u, 10u)));
+                x[h2][3] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be1), 0u, 10u)));
+            }
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+                stage[(4 * q + c4) * P::RPW + pr] = pack_f16x2(x[0][c4], x[1][c4]);
+        }
+    };
+
+    // ---- contraction of tile f: lane (r16 = lane % 16, kg = lane / 16)
+    //   A: W_t[i = r16][32 ks + 8 kg + e];  B: rows 16 b + 32 ks + 8 kg + e of block b = r16;
+    //   D: spectra 16 b + 4 kg + e of block b = r16
+    const int r16 = lane & 15, kg = lane >> 4;
+    const int myb = r16;
+    auto contract = [&](int f) {
+        const int b = f & 1;
+        const Geo G = geometry(f);
+        const int npass = __builtin_amdgcn_readfirstlane(max(max(wred[b][0][2], wred[b][1][2]), max(wred[b][2][2], wred[b][3][2])));
+        const int F0 = mb + f * FM_SPEC;
+        const int64_t row0 = int64_t(F0) - TK + 1;
+        int my_pass[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            my_pass[e] = pass_of[b][16 * myb + 4 * kg + e];
+        // two halves of 8 columns; each half's outputs are stored before the
+        // next.  Within a half, CB columns' operands are read together and
+        // their MFMAs issued back to back (a pass's delay is the same for
+        // every column); CB is what the registers allow beside the next
+        // tile's staged words.
+        constexpr int CB = P::KS > 1 ? 1 : (Mx<PREC>::split ? 2 : 4);
+#pragma unroll 1
+        for (int half = 0; half < 2; ++half) {
+            f32x4 acc[8];
+#pragma unroll
+            for (int c4 = 0; c4 < 8; c4 += CB) {
+                const int col0 = 16 * wave + 8 * half + c4;
+                op ah[CB][P::KS], al[CB][P::KS];
+#pragma unroll
+                for (int cl = 0; cl < CB; ++cl) {
+#pragma unroll
+                    for (int ks = 0; ks < P::KS; ++ks) {
+                        const int o = 16 + 32 * ks + 8 * kg - r16;
+                        const uint32_t *z0 = &zd[0][col0 + cl][o];
+                        ah[cl][ks] = __builtin_bit_cast(op, (u32x4{z0[0], z0[2], z0[4], z0[6]}));
+                        if constexpr (Mx<PREC>::split) {
+                            const uint32_t *z1 = &zd[NPART - 1][col0 + cl][o];
+                            al[cl][ks] = __builtin_bit_cast(op, (u32x4{z1[0], z1[2], z1[4], z1[6]}));
+                        }
+                    }
+                    acc[c4 + cl] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll 1
+                for (int ps = 0; ps < npass; ++ps) {
+                    const int c = min(max(pdel[b][myb][ps], G.cmin), G.cmax);
+                    f32x4 d[CB];
+#pragma unroll
+                    for (int cl = 0; cl < CB; ++cl)
+                        d[cl] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < P::KS; ++ks) {
+                        const int rho = 16 * myb + 32 * ks + 8 * kg;
+                        op bh[CB], bl[CB];
+#pragma unroll
+                        for (int cl = 0; cl < CB; ++cl) {
+                            const int t = t0 + col0 + cl;
+                            if (G.staged) {
+                                const int u = col0 + cl + G.cmax - c + G.u0;
+                                const uint32_t *sp = stage + u * P::RPW + rho / 2;
+                                const u32x4 v4 = {sp[0], sp[1], sp[2], sp[3]};
+                                if constexpr (PREC == FE_PREC_FP16) {
+                                    bh[cl] = __builtin_bit_cast(op, v4);    // staged FP16 pairs are the operand
+                                } else {
+#pragma unroll
+                                    for (int w = 0; w < 4; ++w) {
+                                        // (scalar conversions: a vector FP16x2 -> FP32x2
+                                        // conversion miscompiled here)
+                                        const float x0 = float(__builtin_bit_cast(_Float16, uint16_t(v4[w])));
+                                        const float x1 = float(__builtin_bit_cast(_Float16, uint16_t(v4[w] >> 16)));
+                                        Mx<PREC>::put(bh[cl], bl[cl], 2 * w, x0);
+                                        Mx<PREC>::put(bh[cl], bl[cl], 2 * w + 1, x1);
+                                    }
+                                }
+                            } else {
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) {
+                                    const int64_t i = int64_t(n2) * (row0 + rho + e) + t - c;
+                                    const int x = i < Ncall ? sample_at(rs, hs, i, H) : 0;
+                                    Mx<PREC>::put(bh[cl], bl[cl], e, float(x));
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int cl = 0; cl < CB; ++cl)
+                            d[cl] = mma16<PREC>(ah[cl][ks], al[cl][ks], bh[cl], bl[cl], d[cl]);
+                    }
+#pragma unroll
+                    for (int cl = 0; cl < CB; ++cl)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (my_pass[e] == ps)
+                                acc[c4 + cl][e] = d[cl][e];
+                }
+            }
+
+            // outputs: lane holds spectra 16 b + 4 kg + e at 8 consecutive columns
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int fl = 16 * myb + 4 * kg + e;
+                const int F = F0 + fl;
+                if (F >= me)
+                    continue;
+                const bool ok = cdel[b][fl] >= 0;
+                const int64_t base = (int64_t(s) * M + F) * n2 + t0 + 16 * wave + 8 * half;
+                if constexpr (GOUT == GOUT_F16) {
+                    uint32_t w[4];
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        const float v0 = ok ? acc[2 * qq][e] * out_scale : 0.f;
+                        const float v1 = ok ? acc[2 * qq + 1][e] * out_scale : 0.f;
+                        w[qq] = pack_f16x2(v0, v1);
+                    }
+                    *reinterpret_cast<u32x4 *>(static_cast<_Float16 *>(gout) + base) = u32x4{w[0], w[1], w[2], w[3]};
+                } else {
+                    // FP32 store; for FP16 streams the value is the FP16-rounded one
+                    f32x4 *dst = reinterpret_cast<f32x4 *>(static_cast<float *>(gout) + base);
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq) {
+                        f32x4 v;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            float x = ok ? acc[4 * qq + r][e] * out_scale : 0.f;
+                            if constexpr (PREC == FE_PREC_FP16)
+                                x = float((_Float16)x);
+                            v[r] = x;
+                        }
+                        dst[qq] = v;
+                    }
+                }
+            }
+        }
+    };
+
+    // ---- tap vectors (once): zt[col][16 + j] = h'[t + 2n j] (scaled), zero
+    // elsewhere; lanes take consecutive columns (coalesced), all loads first
     {
         const int col = tid & 63, j0 = tid >> 6;
         constexpr int JPT = (TK + 3) / 4;
         float hv[JPT];
 #pragma unroll
-        for (int q = 0; q < JPT; ++q) {
-            const int j = j0 + 4 * q;
-            hv[q] = j < TK ? taps[(t0 + col) + int64_t(n2) * j] * tap_scale : 0.f;
+        for (int qq = 0; qq < JPT; ++qq) {
+            const int j = j0 + 4 * qq;
+            hv[qq] = j < TK ? taps[(t0 + col) + int64_t(n2) * j] * tap_scale : 0.f;
         }
         for (int v = j0; v < P::ZL; v += 4)
             if (v < 16 || v >= 16 + TK)
-                for (int part = 0; part < (Mx<PREC>::split ? 2 : 1); ++part)
+                for (int part = 0; part < NPART; ++part)
                     zt[part][col][v] = 0;
 #pragma unroll
-        for (int q = 0; q < JPT; ++q) {
-            const int j = j0 + 4 * q;
+        for (int qq = 0; qq < JPT; ++qq) {
+            const int j = j0 + 4 * qq;
             if (j < TK) {
-                const float h = hv[q];
+                const float hh = hv[qq];
                 if constexpr (Mx<PREC>::split) {
-                    const __bf16 hh = (__bf16)h;
-                    const __bf16 hl = (__bf16)(h - (float)hh);
-                    zt[0][col][16 + j] = __builtin_bit_cast(uint16_t, hh);
-                    zt[1][col][16 + j] = __builtin_bit_cast(uint16_t, hl);
+                    const __bf16 h1 = (__bf16)hh;
+                    const __bf16 h2 = (__bf16)(hh - (float)h1);
+                    zt[0][col][16 + j] = __builtin_bit_cast(uint16_t, h1);
+                    zt[1][col][16 + j] = __builtin_bit_cast(uint16_t, h2);
                 } else {
-                    zt[0][col][16 + j] = __builtin_bit_cast(uint16_t, (_Float16)h);
+                    zt[0][col][16 + j] = __builtin_bit_cast(uint16_t, (_Float16)hh);
                 }
             }
         }
     }
+    // ---- the first two tiles' delays
+    split_tile(fb, load_delay(fb));
+    if (fb + 1 < fe)
+        split_tile(fb + 1, load_delay(fb + 1));
     __syncthreads();
-    if (cdel[tid] >= 0) {
-        atomicMin(&red[0], cdel[tid]);
-        atomicMax(&red[1], cdel[tid]);
-    }
-    // passes: block b's spectra in order; a new pass starts where the delay
-    // changes (invalid spectra keep the current pass and are zeroed later)
-    if (tid < 16) {
-        const int b = tid;
-        int cur = -1;
-        for (int i = 0; i < 16; ++i)
-            if (cdel[16 * b + i] >= 0) {
-                cur = cdel[16 * b + i];
-                break;
-            }
-        if (cur < 0)
-            cur = 0;
-        int p = 0;
-        pdel[b][0] = cur;
-        for (int i = 0; i < 16; ++i) {
-            const int c = cdel[16 * b + i];
-            if (c >= 0 && c != cur) {
-                ++p;
-                cur = c;
-                pdel[b][p] = cur;
-            }
-            pass_of[16 * b + i] = uint8_t(p);
-        }
-        for (int q = p + 1; q < 16; ++q)
-            pdel[b][q] = cur;
-        atomicMax(&red[2], p + 1);
-    }
     for (int e = tid; e < NPART * FM_COLS * P::ZL; e += 256) {
         const int part = e / (FM_COLS * P::ZL);
         const int col = (e / P::ZL) % FM_COLS, v = e % P::ZL;
@@ -1076,187 +1353,32 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
         const uint32_t hi = v + 1 < P::ZL ? zt[part][col][v + 1] : 0u;
         zd[part][col][v] = lo | (hi << 16);
     }
-    __syncthreads();
-    int cmin = red[0], cmax = red[1];
-    if (cmax < 0)
-        cmin = cmax = 0;                                     // no valid spectrum
-    const int npass = red[2];
-    // staged columns start on a 4-sample group (5 whole bytes): staged column
-    // u holds sample 2n r + 4 gq0 + u of row r, gq0 = floor((t0 - cmax) / 4)
-    const int gq0 = (t0 - cmax) >> 2;                        // arithmetic shift = floor
-    const int u0 = (t0 - cmax) - 4 * gq0;                    // 0 .. 3
-    const int NGR = (FM_COLS + cmax - cmin + u0 + 3) >> 2;   // groups per staged row
-    const bool staged = 4 * NGR <= FM_WMAX;
-    const int64_t row0 = int64_t(F0) - TK + 1;               // call-relative row of staged row 0
-
-    // ---- stage rows [row0, row0 + ROWS) as FP16 row pairs.  Thread
-    // (q = tid % 32, prs = tid / 32) takes group q (4 samples in 5 bytes) of
-    // row pairs prs, prs + 8, ...: each group read as two aligned dwords (in
-    // range: every chunk and history row is a multiple of 4 bytes), all of a
-    // thread's loads issued before the first conversion.
-    if (staged) {
-        constexpr int PRS = P::ROWS / 2;                     // row pairs
-        constexpr int IT = (PRS + 7) / 8;
-        const int q = tid & 31, prs = tid >> 5;
-        const int gpr = n2 >> 2;                             // groups per row
-        const int hist_g = H >> 2;
-        const int ncall_g = int(Ncall >> 2);
-        const int ga0 = gpr * int(row0) + gq0 + q;           // group of (row0, q)
-        uint32_t dw[IT][2][2];
-        uint32_t off[IT][2];
-        if (q < NGR) {
-#pragma unroll
-            for (int k = 0; k < IT; ++k) {
-                const int pr = prs + 8 * k;
-#pragma unroll
-                for (int h2 = 0; h2 < 2; ++h2) {
-                    const int ga = ga0 + gpr * (2 * pr + h2);
-                    const bool in_hist = ga < 0;
-                    const bool ok = pr < PRS && ga < ncall_g;
-                    const int byte = 5 * (in_hist ? ga + hist_g : ga);
-                    const uint8_t *base = in_hist ? hs : rs;
-                    // unconditional loads (offset 0 stands in for rows outside
-                    // the call; their words are zeroed after the load)
-                    const uint32_t *p32 = reinterpret_cast<const uint32_t *>(base) + (ok ? byte >> 2 : 0);
-                    const uint32_t w0 = p32[0], w1 = p32[1];
-                    dw[k][h2][0] = ok ? w0 : 0u;
-                    dw[k][h2][1] = ok ? w1 : 0u;
-                    off[k][h2] = uint32_t(byte & 3);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < IT; ++k) {
-                const int pr = prs + 8 * k;
-                if (pr >= PRS)
-                    break;
-                float x[2][4];
-#pragma unroll
-                for (int h2 = 0; h2 < 2; ++h2) {
-                    const uint32_t o = off[k][h2];
-                    // big-endian bytes b0..b3 and (b3, b4) of the group
-                    const uint32_t be0 = __builtin_amdgcn_perm(dw[k][h2][1], dw[k][h2][0], 0x00010203u + 0x01010101u * o);
-                    const uint32_t be1 = __builtin_amdgcn_perm(dw[k][h2][1], dw[k][h2][0],
-                                                               0x0C0C0000u | ((o + 3u) << 8) | (o + 4u));
-                    x[h2][0] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 22u, 10u)));
-                    x[h2][1] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 12u, 10u)));
-                    x[h2][2] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be0), 2u, 10u)));
-                    x[h2][3] = float(int32_t(__builtin_amdgcn_sbfe(int32_t(be1), 0u, 10u)));
-                }
-#pragma unroll
-                for (int c4 = 0; c4 < 4; ++c4)
-                    stage[(4 * q + c4) * P::RPW + pr] = pack_f16x2(x[0][c4], x[1][c4]);
-            }
-        }
-    }
+    passes(fb);
+    if (fb + 1 < fe)
+        passes(fb + 1);
+    __syncthreads();                                         // zd and the pass tables are out; zt is free
+    stage_load(fb);
+    stage_write(fb);
+    double d2 = fb + 2 < fe ? load_delay(fb + 2) : 0.0;
     __syncthreads();
 
-    // ---- contraction: lane (r16 = lane % 16, kg = lane / 16)
-    //   A: W_t[i = r16][32 ks + 8 kg + e];  B: rows 16 b + 32 ks + 8 kg + e of block b = r16;
-    //   D: spectra 16 b + 4 kg + e of block b = r16
-    const int r16 = lane & 15, kg = lane >> 4;
-    const int myb = r16;
-    int my_pass[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-        my_pass[e] = pass_of[16 * myb + 4 * kg + e];
-    // two halves of 8 columns; each half's outputs are stored before the next
-#pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-        f32x4 acc[8];
-#pragma unroll
-        for (int cl = 0; cl < 8; ++cl) {
-            const int col = 16 * wave + 8 * half + cl;
-            const int t = t0 + col;
-            op ah[P::KS], al[P::KS];
-#pragma unroll
-            for (int ks = 0; ks < P::KS; ++ks) {
-                const int o = 16 + 32 * ks + 8 * kg - r16;
-                ah[ks] = __builtin_bit_cast(op, (u32x4{zd[0][col][o], zd[0][col][o + 2], zd[0][col][o + 4],
-                                                       zd[0][col][o + 6]}));
-                if constexpr (Mx<PREC>::split)
-                    al[ks] = __builtin_bit_cast(op, (u32x4{zd[NPART - 1][col][o], zd[NPART - 1][col][o + 2],
-                                                           zd[NPART - 1][col][o + 4], zd[NPART - 1][col][o + 6]}));
-            }
-            f32x4 res = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-            for (int ps = 0; ps < npass; ++ps) {
-                // blocks without a valid spectrum carry delay 0: keep the read in the staged range
-                const int c = min(max(pdel[myb][ps], cmin), cmax);
-                f32x4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int ks = 0; ks < P::KS; ++ks) {
-                    const int rho = 16 * myb + 32 * ks + 8 * kg;
-                    op bh, bl;
-                    if (staged) {
-                        const int u = col + cmax - c + u0;
-                        const uint32_t *sp = stage + u * P::RPW + rho / 2;
-                        const u32x4 v4 = {sp[0], sp[1], sp[2], sp[3]};
-                        if constexpr (PREC == FE_PREC_FP16) {
-                            bh = __builtin_bit_cast(op, v4);            // staged FP16 pairs are the operand
-                        } else {
-#pragma unroll
-                            for (int w = 0; w < 4; ++w) {
-                                // (scalar conversions: a vector FP16x2 -> FP32x2 conversion
-                                // miscompiled here)
-                                const float x0 = float(__builtin_bit_cast(_Float16, uint16_t(v4[w])));
-                                const float x1 = float(__builtin_bit_cast(_Float16, uint16_t(v4[w] >> 16)));
-                                Mx<PREC>::put(bh, bl, 2 * w, x0);
-                                Mx<PREC>::put(bh, bl, 2 * w + 1, x1);
-                            }
-                        }
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const int64_t i = int64_t(n2) * (row0 + rho + e) + t - c;
-                            const int x = i < Ncall ? sample_at(rs, hs, i, H) : 0;
-                            Mx<PREC>::put(bh, bl, e, float(x));
-                        }
-                    }
-                    d = mma16<PREC>(ah[ks], al[ks], bh, bl, d);
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (my_pass[e] == ps)
-                        res[e] = d[e];
-            }
-            acc[cl] = res;
-        }
-
-        // outputs: lane holds spectra 16 b + 4 kg + e at 8 consecutive columns
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int fl = 16 * myb + 4 * kg + e;
-            const int F = F0 + fl;
-            if (F >= me)
-                continue;
-            const bool ok = cdel[fl] >= 0;
-            const int64_t base = (int64_t(s) * M + F) * n2 + t0 + 16 * wave + 8 * half;
-            if constexpr (GOUT == GOUT_F16) {
-                uint32_t w[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float v0 = ok ? acc[2 * q][e] * out_scale : 0.f;
-                    const float v1 = ok ? acc[2 * q + 1][e] * out_scale : 0.f;
-                    w[q] = pack_f16x2(v0, v1);
-                }
-                *reinterpret_cast<u32x4 *>(static_cast<_Float16 *>(gout) + base) = u32x4{w[0], w[1], w[2], w[3]};
-            } else {
-                // FP32 store; for FP16 streams the value is the FP16-rounded one
-                f32x4 *dst = reinterpret_cast<f32x4 *>(static_cast<float *>(gout) + base);
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    f32x4 v;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        float x = ok ? acc[4 * q + r][e] * out_scale : 0.f;
-                        if constexpr (PREC == FE_PREC_FP16)
-                            x = float((_Float16)x);
-                        v[r] = x;
-                    }
-                    dst[q] = v;
-                }
-            }
-        }
+    // ---- the chain: tile f+1's rows and tile f+3's delays are loaded while
+    // tile f is contracted; tile f+2 is analysed behind it
+    for (int f = fb; f < fe; ++f) {
+        if (f + 1 < fe)
+            stage_load(f + 1);
+        const double d3 = f + 3 < fe ? load_delay(f + 3) : 0.0;
+        contract(f);
+        __syncthreads();                                     // the staging area and tile f's tables are free
+        if (f + 1 < fe)
+            stage_write(f + 1);
+        if (f + 2 < fe)
+            split_tile(f + 2, d2);
+        d2 = d3;
+        __syncthreads();
+        if (f + 2 < fe)
+            passes(f + 2);
+        __syncthreads();
     }
 }
 
@@ -1814,15 +1936,20 @@ void launch_fir_mfma_T(const fe_stream *s, const uint8_t *raw, int64_t N, const 
     const int M = int(N / n2);
     const int ctiles = n2 / FM_COLS;
     const int ftiles = (me - mb + FM_SPEC - 1) / FM_SPEC;
-    const int64_t blocks = int64_t(2 * s->A) * ftiles * ctiles;
+    // chains of consecutive spectrum tiles per workgroup (the taps are
+    // loaded once per chain and each tile's rows are fetched during the
+    // previous tile's contraction); about 1024 workgroups, two per CU
+    const int64_t tiles = int64_t(2 * s->A) * ftiles * ctiles;
+    const int chain = int(std::min<int64_t>(ftiles, std::max<int64_t>(1, tiles / 1024)));
+    const int64_t blocks = int64_t(2 * s->A) * ((ftiles + chain - 1) / chain) * ctiles;
     if (PREC == FE_PREC_FP16 && !g_f32)
         hipLaunchKernelGGL((fir_mfma_kernel<TK, PREC, GOUT_F16>), dim3(unsigned(blocks)), dim3(256), 0,
                            s->stream, raw, N * 5 / 4, N, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps,
-                           s->tap_scale, s->out_scale, delays, g, n2, M, s->D, mb, me, ctiles, ftiles);
+                           s->tap_scale, s->out_scale, delays, g, n2, M, s->D, mb, me, ctiles, ftiles, chain);
     else
         hipLaunchKernelGGL((fir_mfma_kernel<TK, PREC, GOUT_F32>), dim3(unsigned(blocks)), dim3(256), 0,
                            s->stream, raw, N * 5 / 4, N, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps,
-                           s->tap_scale, s->out_scale, delays, g, n2, M, s->D, mb, me, ctiles, ftiles);
+                           s->tap_scale, s->out_scale, delays, g, n2, M, s->D, mb, me, ctiles, ftiles, chain);
 }
 
 void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g,

@@ -109,12 +109,14 @@ def stepped_delays(w, every, rng):
 # FIR stage
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,T,step", [(1024, 16, 0), (256, 4, 5), (4096, 16, 3), (512, 24, 7),
-                                      (256, 32, 1), (2048, 13, 0)])
-def test_fir_impulses_fp16_bit_exact(n, T, step):
-    _say("mfma fir impulses n=%d T=%d step=%d" % (n, T, step))
+@pytest.mark.parametrize("n,T,step,M", [(1024, 16, 0, 80), (256, 4, 5, 80), (4096, 16, 3, 80), (512, 24, 7, 80),
+                                        (256, 32, 1, 80), (2048, 13, 0, 80),
+                                        # tiles whose rows all lie inside the call
+                                        # (the staging path without per-load checks)
+                                        (256, 16, 40, 1100), (512, 32, 0, 900)])
+def test_fir_impulses_fp16_bit_exact(n, T, step, M):
+    _say("mfma fir impulses n=%d T=%d step=%d M=%d" % (n, T, step, M))
     S, A = 4, 2
-    M = 80
     shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
     w = synth.make_workload(shape, 99)
     x = np.zeros_like(w.x)
@@ -142,7 +144,7 @@ def test_fir_impulses_fp16_bit_exact(n, T, step):
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n,T,A,S,M,every", [(1024, 16, 1, 4, 300, 0), (4096, 16, 2, 4, 40, 5),
                                              (256, 24, 1, 8, 520, 3), (512, 32, 2, 2, 266, 1),
-                                             (2048, 7, 1, 4, 64, 11)])
+                                             (2048, 7, 1, 4, 64, 11), (256, 16, 2, 4, 1100, 20)])
 def test_fir_stage_error(prec, n, T, A, S, M, every):
     _say("mfma fir %s n=%d T=%d A=%d M=%d every=%d" % (prec, n, T, A, M, every))
     shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
