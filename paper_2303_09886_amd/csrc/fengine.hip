@@ -834,7 +834,7 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
                     if (MODE == OUT_PREQUANT)
                         y_out[sp * NL + k] = Y;
                     else
-                        q16[k] = uint16_t(quant4(Y.x, Y.y, 0.f, 0.f));
+                        q16[dsel * NS + kk] = uint16_t(quant4(Y.x, Y.y, 0.f, 0.f));   // plane dsel, coalesced
                 }
             }
         }
@@ -1643,9 +1643,12 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
 
 constexpr int CT = 64;                     // tile edge (spectra and channels)
 
+// spec8 holds each spectrum either in channel order or, for the two-level
+// FFT (ns = n/16), as 16 planes of ns channels: position j = d ns + k' is
+// channel d + 16 k'.  A tile never straddles planes (ns is a multiple of 64).
 __global__ __launch_bounds__(256) void corner_turn_kernel(
     const uint32_t *__restrict__ spec8, int8_t *__restrict__ out, int M, int n, int S,
-    int ftiles, int ktiles)
+    int ftiles, int ktiles, int ns)
 {
     // t16[f][2k + p] = (re, im) of channel k0+k, pol p, spectrum F0+f
     __shared__ uint16_t t16[CT][2 * CT + 2];
@@ -1673,10 +1676,13 @@ __global__ __launch_bounds__(256) void corner_turn_kernel(
     // write: lane = spectrum, so a wave stores 64 consecutive dwords of a channel
     const int f = tid & (CT - 1);
     const int F = F0 + f;
+    // channel of tile position k: c0 + cs k
+    const int c0 = ns ? k0 / ns + 16 * (k0 % ns) : k0;
+    const int cs = ns ? 16 : 1;
     if (F < M) {
         for (int k = tid >> 6; k < CT; k += 256 / CT) {
             const uint32_t d = *reinterpret_cast<const uint32_t *>(&t16[f][2 * k]);
-            const int64_t idx = ((int64_t(a) * (M / S) + F / S) * n + k0 + k) * S + (F % S);
+            const int64_t idx = ((int64_t(a) * (M / S) + F / S) * n + c0 + cs * k) * S + (F % S);
             reinterpret_cast<uint32_t *>(out)[idx] = d;
         }
     }
@@ -2079,8 +2085,10 @@ void launch_post(const fe_stream *s, int M, const double *delays, const double *
 void launch_corner_turn(const fe_stream *s, int M, int8_t *out)
 {
     const int ftiles = (M + CT - 1) / CT, ktiles = s->n / CT;
+    // the two-level FFT (n > 8192, FP32) leaves its spectra as 16 residue planes
+    const int ns = s->n > 8192 ? s->n / 16 : 0;
     hipLaunchKernelGGL(corner_turn_kernel, dim3(unsigned(s->A * ftiles * ktiles)), dim3(256), 0,
-                       s->stream, s->d_spec8, out, M, s->n, s->S, ftiles, ktiles);
+                       s->stream, s->d_spec8, out, M, s->n, s->S, ftiles, ktiles, ns);
 }
 
 unsigned grid_for(int64_t work, int threads)

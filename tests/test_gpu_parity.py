@@ -146,6 +146,32 @@ def test_fir_impulses_bit_exact(n, T, step):
     assert np.array_equal(g, ref["g"].astype(np.float32))
 
 
+@pytest.mark.parametrize("n,T,step", [(1024, 16, 1), (512, 16, 2), (256, 24, 3), (256, 32, 2),
+                                      (1024, 16, 4), (512, 8, 1)])
+def test_fir_short_spans_bit_exact(n, T, step):
+    """Integer-delay steps every 1-4 spectra: spans of one delay shorter
+    than a group take the one-output-at-a-time path; impulses pin it
+    exactly as in test_fir_impulses_bit_exact."""
+    _say("fir short spans n=%d T=%d step=%d" % (n, T, step))
+    S, A, M = 4, 2, 40
+    shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 77)
+    x = np.zeros_like(w.x)
+    rng = np.random.default_rng(n + 3 * T + step)
+    spacing = 2 * n * (T + 2) + 3
+    for a in range(A):
+        for p in range(2):
+            pos = np.arange(rng.integers(0, 2 * n), w.total, spacing)
+            x[a, p, pos] = rng.choice([-512, 511, 1, -1, 300], size=pos.size)
+    w.x, w.raw = x, synth.pack10(x)
+    ramp = np.floor(np.arange(M) / step)
+    w.delays[:] = np.floor(rng.uniform(0, 60, size=(A, 2, 1))) + ramp[None, None, :]
+    g, status = gpu_run(w, w.total, mode="fir")
+    assert status == fe.FE_OK
+    ref = oracle_run(w, want=("g",))
+    assert np.array_equal(g, ref["g"].astype(np.float32))
+
+
 @pytest.mark.parametrize("n,T,A,S,M", [(1024, 16, 1, 4, 44), (4096, 16, 2, 4, 36), (256, 8, 3, 2, 70)])
 def test_fir_matches_oracle(n, T, A, S, M):
     _say("fir noise n=%d T=%d A=%d M=%d" % (n, T, A, M))
