@@ -1554,7 +1554,9 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
     const int n32 = lane & 31, h = lane >> 5;
     const int64_t sp = (int64_t(a) * 2 + p) * M + F;
 
-    // stage-0 operands straight from g: in(gam, j) = gam + (n/16) j
+    // stage-0 operands straight from g: in(gam, j) = gam + (n/16) j (loaded
+    // non-temporally, like the FP32 kernel: g is read once, and the int8
+    // spectra written here should stay cached for the corner turn)
     op Bh[P::CPW][2], Bl[P::CPW][2];
 #pragma unroll
     for (int u = 0; u < P::CPW; ++u) {
@@ -1568,14 +1570,15 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int j = 8 * kap + 4 * h + e;
-                    w[e] = valid ? static_cast<const uint32_t *>(g)[sp * N + gam + P::G * j] : 0u;
+                    w[e] = valid ? __builtin_nontemporal_load(static_cast<const uint32_t *>(g) + sp * N + gam + P::G * j)
+                                 : 0u;
                 }
                 Bh[u][kap] = __builtin_bit_cast(op, w);
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int j = 8 * kap + 4 * h + e;
-                    const float2 v = valid ? static_cast<const float2 *>(g)[sp * N + gam + P::G * j]
+                    const float2 v = valid ? load_nt(static_cast<const float2 *>(g) + sp * N + gam + P::G * j)
                                            : make_float2(0.f, 0.f);
                     Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e, v.x);
                     Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e + 1, v.y);
