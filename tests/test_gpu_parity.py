@@ -307,7 +307,34 @@ def test_host_validation_with_live_stream():
     with pytest.raises(fe.FEngineError) as e:
         st.channelize(dev(raw), 2 * w.total, dev(d), dev(p), dev(w.gains), o)
     assert e.value.status == fe.FE_ESIZE
+    # an empty call is not a whole number of heaps either
+    with pytest.raises(fe.FEngineError) as e:
+        st.channelize(dev(raw), 0, dev(d), dev(p), dev(w.gains), o)
+    assert e.value.status == fe.FE_EINVAL
+    assert st.status() == fe.FE_OK                 # refused calls leave the stream untouched
     st.close()
+
+
+@pytest.mark.parametrize("T", [16, 32])
+def test_largest_delay_matches_oracle(T):
+    """Coarse delays at the largest allowed value D (d in [D - 0.5, D + 0.5))
+    and just below it, over two calls: the FIR reads the most history rows
+    and the stream keeps the deepest tail."""
+    n, S, M, calls, D = 256, 4, 48, 2, 128
+    _say("largest delay T=%d" % T)
+    shape = synth.Shape(n=n, taps=T, antennas=1, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 31 + T, total=2 * n * M * calls)
+    F = np.arange(w.delays.shape[2])
+    w.delays[0, 0] = D + 0.49 - 0.98 * (F % 7) / 7.0      # c = D throughout
+    w.delays[0, 1] = D - 0.51 + 0.3 * (F % 2)              # c alternates D - 1, D
+    y, status = gpu_run(w, 2 * n * M, mode="prequant", max_delay=D)
+    assert status == fe.FE_OK
+    ref = oracle_run(w, want=("y", "q"), max_delay=D)
+    nw, el = compare.assert_prequant_close(y, ref["y"])
+    _say("  Y normwise %.3g elementwise %.3g" % (nw, el))
+    q, status = gpu_run(w, 2 * n * M, mode="int8", max_delay=D)
+    assert status == fe.FE_OK
+    check_int8(q, ref, S, "largest delay")
 
 
 # --------------------------------------------------------------------------
