@@ -562,18 +562,24 @@ __device__ __forceinline__ void fft_rest(float2 *buf, int tp, const float2 *tw_a
 
 enum { OUT_INT8 = 0, OUT_PREQUANT = 1 };
 
-// Four values to four int8 in one dword (byte i = value i): round half to
-// even, saturate to [-127, 127].  The rounded value plus 128 (exact) goes
-// into its byte as an unsigned 8-bit integer; flipping the top bit of every
-// byte then gives the two's complement code.
+// Four values to four int8 in one dword (byte i = value i): saturate to
+// [-127, 127], round half to even.  Clamping first gives the same result as
+// rounding first (the bounds are integers).  Adding 1.5 * 2^23 rounds the
+// clamped value to an integer r in the float's own rounding (to nearest,
+// ties to even: the sum's unit in the last place is 1) and leaves
+// 0x400000 + r in its mantissa, whose low byte is r in two's complement.
+// Finite inputs only.
 __device__ __forceinline__ uint32_t quant4(float a, float b, float c, float d)
 {
-    uint32_t w = 0;
-    w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(rintf(a), -127.f, 127.f) + 128.f, 0u, w);
-    w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(rintf(b), -127.f, 127.f) + 128.f, 1u, w);
-    w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(rintf(c), -127.f, 127.f) + 128.f, 2u, w);
-    w = __builtin_amdgcn_cvt_pk_u8_f32(__builtin_amdgcn_fmed3f(rintf(d), -127.f, 127.f) + 128.f, 3u, w);
-    return w ^ 0x80808080u;
+    constexpr float kRound = 12582912.0f;                 // 1.5 * 2^23
+    const uint32_t ya = __builtin_bit_cast(uint32_t, __builtin_amdgcn_fmed3f(a, -127.f, 127.f) + kRound);
+    const uint32_t yb = __builtin_bit_cast(uint32_t, __builtin_amdgcn_fmed3f(b, -127.f, 127.f) + kRound);
+    const uint32_t yc = __builtin_bit_cast(uint32_t, __builtin_amdgcn_fmed3f(c, -127.f, 127.f) + kRound);
+    const uint32_t yd = __builtin_bit_cast(uint32_t, __builtin_amdgcn_fmed3f(d, -127.f, 127.f) + kRound);
+    // byte selectors 0-3 take the second operand, 4-7 the first, 0x0c gives 0
+    const uint32_t lo = __builtin_amdgcn_perm(yb, ya, 0x0c0c0400u);       // (a, b, 0, 0)
+    const uint32_t hi = __builtin_amdgcn_perm(yd, yc, 0x04000c0cu);       // (0, 0, c, d)
+    return lo | hi;
 }
 
 // Per-spectrum phase tables: exp(i(phi - pi k tau / n)) = ph_hi[k >> 6] *
