@@ -180,11 +180,14 @@ fe_status fe_debug_unpack10(const uint8_t *raw, int64_t first, int64_t count,
 
 /* Time the stream's launch choices on the caller's buffers (an fe_channelize
  * call's arguments; `iters` timed calls per candidate, HIP events on the
- * stream's HIP stream) and keep the fastest.  The candidates are the FIR's
- * run length -- how many consecutive batches of spectra one workgroup
- * filters (a batch is 64 spectra, 48 for 24 taps), trading tap reloads
- * against parallelism (1, 2, 4, 8 batches, or the per-launch default);
- * reduced-precision streams have one candidate.
+ * stream's HIP stream) and keep the fastest.  The candidates set the FIR's
+ * schedule: for FP32 streams its run length -- how many consecutive batches
+ * of spectra one workgroup filters (a batch is 64 spectra, 48 for 24 taps),
+ * trading tap reloads against parallelism; for FP16/BF16 streams the chain
+ * length of the matrix-core FIR -- how many consecutive 256-spectrum tiles
+ * one workgroup walks (its taps loaded once, each tile's rows fetched during
+ * the previous tile's contraction).  Candidates: 1, 2, 4, 8, or the
+ * per-launch default.
  * The timing calls advance the stream like real calls, so the stream is
  * reset (fe_stream_reset) before returning.  Synchronizes.  *choice (may be
  * NULL) receives the chosen run length (0 = per-launch default). */
@@ -192,8 +195,9 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
                              const double *delays, const double *phases, const float *gains,
                              int8_t *out, int iters, int *choice);
 
-/* Set the FIR run length directly (0 = per-launch default, else 1..64
- * batches of spectra as above). */
+/* Set the FIR schedule directly (0 = per-launch default, else 1..64:
+ * batches of spectra per run (FP32) or tiles per chain (FP16/BF16), as
+ * above). */
 fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches);
 
 /* ---- Batches of streams ------------------------------------------------ */

@@ -1747,7 +1747,8 @@ constexpr int EV_PER_CALL = 5;
 struct fe_stream {
     int n, T, Tk, A, S, D, H;
     int prec;               // FE_PREC_*
-    int fir_batches;        // FIR run length in batches of spectra (0: chosen per launch)
+    int fir_batches;        // FIR schedule: run length in batches of spectra (FP32) or
+                            // tiles per chain (matrix-core FIR); 0: chosen per launch
     float tap_scale;        // FP16 mode: taps scaled by 2^sc on the matrix cores
     float out_scale;        // 2^-sc, applied to the FIR's FP32 result
     int64_t max_samples;
@@ -1955,7 +1956,9 @@ void launch_fir_mfma_T(const fe_stream *s, const uint8_t *raw, int64_t N, const 
     // loaded once per chain and each tile's rows are fetched during the
     // previous tile's contraction); about 1024 workgroups, two per CU
     const int64_t tiles = int64_t(2 * s->A) * ftiles * ctiles;
-    const int chain = int(std::min<int64_t>(ftiles, std::max<int64_t>(1, tiles / 1024)));
+    int chain = int(std::min<int64_t>(ftiles, std::max<int64_t>(1, tiles / 1024)));
+    if (s->fir_batches > 0)
+        chain = std::min(ftiles, s->fir_batches);           // set by fe_stream_autotune
     const int64_t blocks = int64_t(2 * s->A) * ((ftiles + chain - 1) / chain) * ctiles;
     if (PREC == FE_PREC_FP16 && !g_f32)
         hipLaunchKernelGGL((fir_mfma_kernel<TK, PREC, GOUT_F16>), dim3(unsigned(blocks)), dim3(256), 0,
@@ -2498,8 +2501,10 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
         return FE_EINVAL;
     // candidates: FIR runs of 1, 2, 4, 8 batches (FP32 FIR only), and the
     // per-launch choice; each timed with HIP events over `iters` calls
+    // FIR run length in batches of spectra (FP32), or spectrum tiles per
+    // workgroup chain (matrix-core FIR); 0 = the per-launch default
     static const int cand[] = {0, 1, 2, 4, 8};
-    const int ncand = s->prec == FE_PREC_FP32 ? 5 : 1;
+    const int ncand = 5;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0)

@@ -127,14 +127,18 @@ def test_batch_member_matches_oracle():
     assert hard == 0
 
 
-def test_autotune_keeps_results():
-    shape = synth.Shape(n=4096, taps=16, antennas=2, samples=1 << 21, spectra_per_heap=16)
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_autotune_keeps_results(prec):
+    # FP16: 1024 spectra, 4 tiles of the matrix-core FIR, so chains of 1, 2 and 4 tiles differ
+    shape = synth.Shape(n=4096, taps=16, antennas=2, samples=1 << (21 if prec == "fp32" else 23),
+                        spectra_per_heap=16)
     w = synth.make_workload(shape, 8)
     raw, d, p = w.chunk(0, shape.samples)
     args = [dev(raw), shape.samples, dev(d), dev(p), dev(w.gains)]
     outs = []
     for tune in (False, True):
-        st = fe.Stream(shape.n, shape.taps, shape.antennas, w.weights, shape.samples, spectra_per_heap=16)
+        st = fe.Stream(shape.n, shape.taps, shape.antennas, w.weights, shape.samples, spectra_per_heap=16,
+                       precision=prec)
         o = out_like(shape)
         if tune:
             choice = st.autotune(*args, o, iters=2)
@@ -145,7 +149,8 @@ def test_autotune_keeps_results():
         st.close()
     assert np.array_equal(outs[0], outs[1])
     for fb in (1, 2, 8):
-        st = fe.Stream(shape.n, shape.taps, shape.antennas, w.weights, shape.samples, spectra_per_heap=16)
+        st = fe.Stream(shape.n, shape.taps, shape.antennas, w.weights, shape.samples, spectra_per_heap=16,
+                       precision=prec)
         st.set_tuning(fb)
         o = out_like(shape)
         st.channelize(*args, o)
