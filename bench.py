@@ -212,7 +212,7 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True):
 def measure_service(chunks: int = 24, seed: int = 3):
     """Streaming service: one wide-band antenna (32768 channels, 16 taps),
     chunks of k * 2^20 samples/pol (k uniform in 1..32), already in pinned
-    host memory.  First as a backlog (every chunk waiting at t = 0:
+    host memory, each with a pinned buffer for its output heaps.  First as a backlog (every chunk waiting at t = 0:
     throughput), then with Poisson arrivals at 70% of that throughput
     (latency under load).  Chunk contents are cut from one generated stretch
     of samples (timing does not depend on them); the rate includes the
@@ -247,7 +247,9 @@ def measure_service(chunks: int = 24, seed: int = 3):
                 p = p_pin[:, s0 * spu:(s0 + k) * spu].contiguous().pin_memory()
             if rate:
                 t += rng.exponential(N * 2 / rate)
-            reqs.append(service.Request(0, raw, N, d, p, g_pin, arrival=t))
+            # the int8 heaps go straight into a pinned buffer of the request
+            out = torch.empty(2 * N, dtype=torch.int8).pin_memory()
+            reqs.append(service.Request(0, raw, N, d, p, g_pin, arrival=t, out=out))
         return reqs
 
     budget = 4 * service.chunk_device_bytes(sh.n, 32 * unit)

@@ -45,6 +45,10 @@ class Request:
     delays  float64 [2][M], phases float64 [2][M]  (M = N / 2n)
     gains   float32 [2][n][2]
     arrival seconds on the loop's clock (0 = loop start)
+    out     optional pinned torch int8 tensor of at least 2N elements: the
+            heaps are copied from the device straight into it; otherwise they
+            pass through a pinned staging slot and ``out`` becomes a numpy
+            copy, [1][M/S][n][S][2][2]
     """
     feed: int
     raw: np.ndarray
@@ -53,8 +57,8 @@ class Request:
     phases: np.ndarray
     gains: np.ndarray
     arrival: float = 0.0
+    out: Optional[object] = None
     # filled in by the service
-    out: Optional[np.ndarray] = None
     admitted: float = -1.0
     done: float = -1.0
 
@@ -130,13 +134,15 @@ class Service:
         ev_k = torch.cuda.Event()
         ev_k.record(self.hip[f])
         self.d2h[f].wait_event(ev_k)
+        own = isinstance(r.out, torch.Tensor) and r.out.is_pinned() and r.out.numel() >= 2 * N
+        dst = r.out.reshape(-1)[:2 * N] if own else slot["out"][:2 * N]
         with torch.cuda.stream(self.d2h[f]):
-            slot["out"][:2 * N].copy_(out.reshape(-1), non_blocking=True)
+            dst.copy_(out.reshape(-1).view(dst.dtype), non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(self.d2h[f])
         r.admitted = now
         # device buffers stay referenced until the event has passed
-        return {"req": r, "event": ev, "keep": (raw, d, ph, g, out), "slot": slot,
+        return {"req": r, "event": ev, "keep": (raw, d, ph, g, out), "slot": slot, "own": own,
                 "shape": tuple(out.shape), "bytes": self.chunk_bytes(N)}
 
     def run(self, requests: List[Request], realtime: bool = True, poll: float = 20e-6) -> Dict:
@@ -166,7 +172,8 @@ class Service:
                     r = job["req"]
                     r.done = time.perf_counter() - t0
                     k = 2 * r.n_samples
-                    r.out = job["slot"]["out"][:k].numpy().reshape(job["shape"]).copy()
+                    if not job["own"]:
+                        r.out = job["slot"]["out"][:k].numpy().reshape(job["shape"]).copy()
                     self.slots.append(job["slot"])
                     used -= job["bytes"]
                 else:

@@ -69,11 +69,16 @@ def alone(works, reqs, n, T, S, max_chunk):
     return outs
 
 
-@pytest.mark.parametrize("realtime", [False, True])
-def test_mixed_equals_alone(realtime):
+@pytest.mark.parametrize("realtime,own_out", [(False, False), (True, False), (False, True)])
+def test_mixed_equals_alone(realtime, own_out):
+    """own_out: the requests bring pinned output buffers (filled by the
+    device directly instead of through the service's staging slots)."""
     n, T, S = 32768, 16, 16
     unit = 2 * n * S
     works, reqs = feeds_and_requests(n, T, S, feeds=3, chunks=4, kmax=3, seed=7)
+    if own_out:
+        for r in reqs:
+            r.out = torch.empty(2 * r.n_samples, dtype=torch.int8).pin_memory()
     max_chunk = 3 * unit
     ref = alone(works, reqs, n, T, S, max_chunk)
     budget = 3 * service.chunk_device_bytes(n, max_chunk)        # about three chunks in flight
@@ -85,7 +90,8 @@ def test_mixed_equals_alone(realtime):
          % ("arrivals" if realtime else "backlog", stats["chunks"], stats["gsamples_per_s"],
             stats["latency_ms_p50"], stats["latency_ms_p99"], stats["peak_inflight_bytes"] / 1e6))
     for i, r in enumerate(reqs):
-        assert r.out is not None and np.array_equal(r.out, ref[i]), i
+        got = r.out.numpy().reshape(ref[i].shape) if own_out else r.out
+        assert got is not None and np.array_equal(got, ref[i]), i
     assert stats["peak_inflight_bytes"] <= budget
 
 
