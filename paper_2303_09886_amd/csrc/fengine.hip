@@ -739,11 +739,19 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void fft_front_kernel(float *__restrict__ g, const float2 *__restrict__ twf,
+                                                        const float2 *__restrict__ gains, float2 *__restrict__ gpl,
                                                         int n, int M, int mb, int me, int A)
 {
     const int gpt = n / 16;                                 // groups per spectrum
     const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
     const int64_t total = int64_t(A) * 2 * (me - mb) * gpt;
+    // Side job for the post kernel: this call's per-channel gains of every
+    // stream into residue-plane order (position d n/16 + k' holds channel
+    // d + 16 k'), so that its lanes read consecutive entries.
+    for (int64_t i = e; i < int64_t(A) * 2 * n; i += int64_t(gridDim.x) * 256) {
+        const int r = int(i % n);
+        gpl[i] = gains[i - r + r / gpt + 16 * (r % gpt)];
+    }
     if (e >= total)
         return;
     const int gam = int(e % gpt);
@@ -820,9 +828,10 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
                 float2 wk[8], gk[8];
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
-                    const int k = dsel + 16 * (tp + NTS * (k8 + r));
-                    wk[r] = untangle[k];
-                    gk[r] = gn[k];
+                    // both tables in residue-plane order: consecutive lanes, consecutive entries
+                    const int pos = dsel * NS + tp + NTS * (k8 + r);
+                    wk[r] = untangle[pos];
+                    gk[r] = gn[pos];
                 }
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
@@ -1756,7 +1765,8 @@ struct fe_stream {
     hipStream_t stream;
     float *d_taps;          // [2n*Tk], zero-padded in front when Tk > T
     float2 *d_tw;           // FFT twiddle blocks
-    float2 *d_untangle;     // exp(-i pi k / n)
+    float2 *d_untangle;     // exp(-i pi k / n) (n > 8192: in residue-plane order)
+    float2 *d_gpl;          // n > 8192: the call's gains in residue-plane order, [A*2][n]
     float2 *d_tw16;         // matrix-stage twiddles [stage][group][16] (reduced modes)
     float2 *d_twf;          // n > 8192: first-level twiddles exp(-2 pi i gam d / n), [n/16][16]
     uint32_t *d_dfta;       // DFT-16 A-operand images [K half][hi, lo][lane][8 x 16 bit]
@@ -2051,16 +2061,16 @@ void launch_post_large(const fe_stream *s, int M, const double *delays, const do
 {
     const int64_t fthreads = int64_t(s->A) * 2 * (me - mb) * (NL / 16);
     hipLaunchKernelGGL(fft_front_kernel, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0, s->stream,
-                       s->d_g, s->d_twf, NL, M, mb, me, s->A);
+                       s->d_g, s->d_twf, reinterpret_cast<const float2 *>(gains), s->d_gpl, NL, M, mb, me, s->A);
     const unsigned blocks = unsigned(s->A * (me - mb) * 2);
     if (y_out)
         hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_PREQUANT>), dim3(blocks), dim3(NL / 128), 0,
-                           s->stream, s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->stream, s->d_g, delays, phases, s->d_gpl, s->d_tw,
                            s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
                            mb, me);
     else
         hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_INT8>), dim3(blocks), dim3(NL / 128), 0,
-                           s->stream, s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->stream, s->d_g, delays, phases, s->d_gpl, s->d_tw,
                            s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
                            mb, me);
 }
@@ -2202,6 +2212,7 @@ void free_stream(fe_stream *s)
     (void)hipFree(s->d_taps);
     (void)hipFree(s->d_tw);
     (void)hipFree(s->d_untangle);
+    (void)hipFree(s->d_gpl);
     (void)hipFree(s->d_tw16);
     (void)hipFree(s->d_twf);
     (void)hipFree(s->d_dfta);
@@ -2302,6 +2313,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
               && hipMalloc(&s->d_dfta, dfta.size() * sizeof(uint32_t)) == hipSuccess
               && hipMalloc(&s->d_tw, tw.size() * sizeof(float2)) == hipSuccess
               && hipMalloc(&s->d_untangle, size_t(n) * sizeof(float2)) == hipSuccess
+              && (n <= 8192 || hipMalloc(&s->d_gpl, size_t(streams) * n * sizeof(float2)) == hipSuccess)
               && hipMalloc(&s->d_hist, hist_bytes) == hipSuccess
               && hipMalloc(&s->d_hist_tmp, hist_bytes) == hipSuccess
               && hipMalloc(&s->d_g, g_floats * sizeof(float)) == hipSuccess
@@ -2318,7 +2330,9 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     std::vector<float2> unt(n);
     for (int k = 0; k < n; ++k) {
         const long double a = -3.141592653589793238462643383279503L * (long double)k / (long double)n;
-        unt[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+        // the two-level FFT reads it in residue-plane order (channel d + 16 k' at d n/16 + k')
+        const int pos = n > 8192 ? (k % 16) * (n / 16) + k / 16 : k;
+        unt[pos] = make_float2(float(std::cos(a)), float(std::sin(a)));
     }
     ok = hipMemcpy(s->d_taps, taps.data(), taps_n * sizeof(float), hipMemcpyHostToDevice) == hipSuccess
          && hipMemcpy(s->d_tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice) == hipSuccess
