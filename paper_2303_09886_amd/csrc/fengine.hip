@@ -610,8 +610,12 @@ __device__ __forceinline__ void phase_tables(float2 *ph_hi, float2 *ph_lo, doubl
 // Steps 3b-6 on one polarization's n-point complex FFT Z held in LDS (natural
 // order, lds_pad layout): real-FFT untangle, phase, gain, then either the
 // int8 pair store or the pre-quantisation store.  Thread tid finishes channel
-// pairs (2j, 2j+1), j = tid + NT i.
-template <int N, int NT, int MODE>
+// pairs (2j, 2j+1), j = tid + NT i.  NT_STORE writes the int8 pairs
+// non-temporally: they then do not stay dirty in the caches, where the next
+// call's FIR would pay for their write-back (a gain where that FIR is bound
+// by its FP32 stores; the matrix-core path keeps them cached for the corner
+// turn).
+template <int N, int NT, int MODE, bool NT_STORE = false>
 __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, const float2 *ph_hi,
                                               const float2 *ph_lo, const float2 *__restrict__ untangle,
                                               const float2 *__restrict__ gn, bool ok, int64_t sp, int tid,
@@ -666,7 +670,11 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
         if (MODE == OUT_PREQUANT) {
             reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
         } else {
-            spec8[sp * (N / 2) + j] = quant4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
+            const uint32_t q = quant4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
+            if constexpr (NT_STORE)
+                __builtin_nontemporal_store(q, spec8 + sp * (N / 2) + j);
+            else
+                spec8[sp * (N / 2) + j] = q;
         }
     }
 }
@@ -718,8 +726,8 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
     __syncthreads();
     fft_rest<N, 1>(buf, tid, tw_all);
 
-    post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
-                               tid, spec8, y_out);
+    post_spectrum<N, NT, MODE, true>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
+                                     tid, spec8, y_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1657,6 +1665,9 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
 // A workgroup moves a tile of 64 spectra x 64 channels of one antenna through
 // LDS: it reads 128-byte rows (one pol, one spectrum, 64 channels) and writes
 // runs of consecutive spectra of one channel (contiguous within a heap).
+// Both sides are non-temporal: the spectra are dead after this read and the
+// heaps are not read again on the device, so neither is left dirty in the
+// caches for the next call's FIR to write back.
 // ---------------------------------------------------------------------------
 
 constexpr int CT = 64;                     // tile edge (spectra and channels)
@@ -1685,7 +1696,7 @@ __global__ __launch_bounds__(256) void corner_turn_kernel(
         const int F = F0 + f;
         uint32_t w = 0;
         if (F < M)
-            w = spec8[((int64_t(a) * 2 + p) * M + F) * (n / 2) + (k0 + kk) / 2];
+            w = __builtin_nontemporal_load(spec8 + ((int64_t(a) * 2 + p) * M + F) * (n / 2) + (k0 + kk) / 2);
         t16[f][2 * kk + p] = uint16_t(w);
         t16[f][2 * (kk + 1) + p] = uint16_t(w >> 16);
     }
@@ -1701,7 +1712,7 @@ __global__ __launch_bounds__(256) void corner_turn_kernel(
         for (int k = tid >> 6; k < CT; k += 256 / CT) {
             const uint32_t d = *reinterpret_cast<const uint32_t *>(&t16[f][2 * k]);
             const int64_t idx = ((int64_t(a) * (M / S) + F / S) * n + c0 + cs * k) * S + (F % S);
-            reinterpret_cast<uint32_t *>(out)[idx] = d;
+            __builtin_nontemporal_store(d, reinterpret_cast<uint32_t *>(out) + idx);
         }
     }
 }
