@@ -610,12 +610,9 @@ __device__ __forceinline__ void phase_tables(float2 *ph_hi, float2 *ph_lo, doubl
 // Steps 3b-6 on one polarization's n-point complex FFT Z held in LDS (natural
 // order, lds_pad layout): real-FFT untangle, phase, gain, then either the
 // int8 pair store or the pre-quantisation store.  Thread tid finishes channel
-// pairs (2j, 2j+1), j = tid + NT i.  NT_STORE writes the int8 pairs
-// non-temporally: they then do not stay dirty in the caches, where the next
-// call's FIR would pay for their write-back (a gain where that FIR is bound
-// by its FP32 stores; the matrix-core path keeps them cached for the corner
-// turn).
-template <int N, int NT, int MODE, bool NT_STORE = false>
+// pairs (2j, 2j+1), j = tid + NT i.  The int8 pairs are stored through the
+// caches: the corner turn reads them next.
+template <int N, int NT, int MODE>
 __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, const float2 *ph_hi,
                                               const float2 *ph_lo, const float2 *__restrict__ untangle,
                                               const float2 *__restrict__ gn, bool ok, int64_t sp, int tid,
@@ -670,11 +667,7 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
         if (MODE == OUT_PREQUANT) {
             reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
         } else {
-            const uint32_t q = quant4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
-            if constexpr (NT_STORE)
-                __builtin_nontemporal_store(q, spec8 + sp * (N / 2) + j);
-            else
-                spec8[sp * (N / 2) + j] = q;
+            spec8[sp * (N / 2) + j] = quant4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
         }
     }
 }
@@ -726,8 +719,8 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
     __syncthreads();
     fft_rest<N, 1>(buf, tid, tw_all);
 
-    post_spectrum<N, NT, MODE, true>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
-                                     tid, spec8, y_out);
+    post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
+                               tid, spec8, y_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1666,8 +1659,8 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
 // LDS: it reads 128-byte rows (one pol, one spectrum, 64 channels) and writes
 // runs of consecutive spectra of one channel (contiguous within a heap).
 // Both sides are non-temporal: the spectra are dead after this read and the
-// heaps are not read again on the device, so neither is left dirty in the
-// caches for the next call's FIR to write back.
+// heaps are not read again on the device, so neither displaces the next
+// call's input from the last-level cache nor is left there dirty.
 // ---------------------------------------------------------------------------
 
 constexpr int CT = 64;                     // tile edge (spectra and channels)
