@@ -23,7 +23,7 @@
  *     of tau samples at channel frequency k/(2n) cycles/sample, so coarse
  *     and fine delay together delay the signal by d;
  *   - quantisation: round half to even, saturate symmetrically to +-127,
- *     decision taken in float32 (the paper's FFT precision).
+ *     decided on the double-precision value itself.
  * Parity of these conventions is fixed by this reading, not by the paper.
  */
 #include "oracle.h"
@@ -183,13 +183,12 @@ void oracle_fine_delay_gain(const double *X, int n, double tau, double phi,
 
 int8_t oracle_quantize(double v)
 {
-    double x = (double)(float)v;                        /* decision in float32 */
     double r, diff;
 
-    if (isnan(x))
+    if (isnan(v))
         return 0;
-    r = floor(x);
-    diff = x - r;
+    r = floor(v);
+    diff = v - r;                                       /* exact in double */
     if (diff > 0.5 || (diff == 0.5 && fmod(r, 2.0) != 0.0))
         r += 1.0;                                       /* nearest, ties to even */
     if (r > 127.0)

@@ -50,8 +50,8 @@ int oracle_rfft_keep(const double *g, int n, double *X);
 void oracle_fine_delay_gain(const double *X, int n, double tau, double phi,
                             const float *gain, double *Y);
 
-/* Step 6: signed 8-bit value of v: v rounded to float32, then to the nearest
- * integer (ties to even), saturated to [-127, 127]. */
+/* Step 6: signed 8-bit value of v: the nearest integer to v (ties to even),
+ * saturated to [-127, 127]. */
 int8_t oracle_quantize(double v);
 
 /* Step 6 corner turn: q[a][p][F][k][2] -> heap[a][F/S][k][F%S][p][2]. */
