@@ -1107,25 +1107,28 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
     };
     uint32_t dw[IT][2][2];
     const int row_bytes = 5 * gpr;                           // multiple of 4
-    // interior tile: every group the staging lanes read lies in the call, so
-    // the words are read without per-load checks at a scalar row pointer plus
-    // one lane offset (the rows of lane pair prs are 2 prs below the
-    // pointer; a group's byte phase is the same in every row)
+    // interior tile: every group the staging lanes read lies in the call (the
+    // first, group gq0 of row row0, and the last), so the words are read
+    // without per-load checks at a scalar row pointer plus one lane offset
+    // (the rows of lane pair prs are 2 prs below the pointer; a group's byte
+    // phase is the same in every row)
     auto interior = [&](int f, const Geo &G) {
         const int row0 = mb + f * FM_SPEC - TK + 1;
-        return G.staged && row0 >= 1 && gpr * (row0 + P::ROWS - 1) + G.gq0 + 31 < ncall_g;
+        return G.staged && gpr * row0 + G.gq0 >= 0 && gpr * (row0 + P::ROWS - 1) + G.gq0 + 31 < ncall_g;
     };
     auto stage_load = [&](int f) {
         const Geo G = geometry(f);
         if (interior(f, G)) {
             const int row0 = mb + f * FM_SPEC - TK + 1;
-            // a group's first byte is 5 (gq0 + q) from its row's start, which
-            // is negative for groups before column 0 (gq0 < 0): the pointer
-            // starts a row early so that the unsigned lane offset stays
-            // positive (the dword index is floored: arithmetic shift)
-            const uint32_t lane_off =
-                uint32_t((2 * prs + 1) * row_bytes + 4 * ((5 * (G.gq0 + q)) >> 2));
-            gptr8 rp = (gptr8)rs + int64_t(row0 - 1) * row_bytes;
+            // gq0 = gpr kr + gr with 0 <= gr < gpr: whole rows kr (negative for
+            // coarse delays past the tile's first column) move the scalar row
+            // pointer; the lane offset keeps the rest, with one row of margin,
+            // so it is never negative (a group's first byte is 5 (gr + q) from
+            // its row's start; the dword index is floored)
+            const int kr = G.gq0 >= 0 ? G.gq0 / gpr : -((gpr - 1 - G.gq0) / gpr);
+            const int gr = G.gq0 - kr * gpr;
+            const uint32_t lane_off = uint32_t((2 * prs + 1) * row_bytes + 4 * ((5 * (gr + q)) >> 2));
+            gptr8 rp = (gptr8)rs + int64_t(row0 - 1 + kr) * row_bytes;
 #pragma unroll
             for (int k = 0; k < IT; ++k) {
 #pragma unroll

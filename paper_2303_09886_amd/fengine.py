@@ -134,6 +134,34 @@ def _hip_stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
+def _need(t, count, what):
+    """Refuse a buffer smaller than the header's layout needs: the kernels
+    would read or write past its end."""
+    if t.numel() < count:
+        raise ValueError("%s holds %d elements, the call needs %d" % (what, t.numel(), count))
+
+
+def call_sizes(n_antennas: int, n_channels: int, n_samples: int) -> dict:
+    """Element counts one call needs (include/fengine.h): raw uint8
+    [A][2][N*5/4], delays and phases float64 [A][2][M], gains float32
+    [A][2][n][2], and each output (int8 heaps, float32 spectra or filtered
+    samples) 2*A*N elements."""
+    N = int(n_samples)
+    streams = 2 * int(n_antennas)
+    M = N // (2 * int(n_channels)) if N > 0 else 0
+    return {"raw": streams * (N * 5 // 4), "delays": streams * M, "phases": streams * M,
+            "gains": streams * int(n_channels) * 2, "out": streams * N}
+
+
+def check_sizes(n_antennas: int, n_channels: int, n_samples: int, **buffers):
+    """Raise ValueError if any given buffer (raw, delays, phases, gains, out)
+    is too small for a call of n_samples samples per polarization."""
+    need = call_sizes(n_antennas, n_channels, n_samples)
+    for name, t in buffers.items():
+        if t is not None:
+            _need(t, need["out" if name in ("out", "y_out", "g_out") else name], name)
+
+
 class Stream:
     """One fe_stream: A antennas x 2 polarizations with state across calls.
 
@@ -210,8 +238,8 @@ class Stream:
 
     def _args(self, raw, n_samples, delays, phases=None, gains=None):
         import torch
-        out = [self._h, _ptr(raw, torch.uint8, "raw"), int(n_samples),
-               _ptr(delays, torch.float64, "delays")]
+        check_sizes(self.A, self.n, n_samples, raw=raw, delays=delays, phases=phases, gains=gains)
+        out = [self._h, _ptr(raw, torch.uint8, "raw"), int(n_samples), _ptr(delays, torch.float64, "delays")]
         if phases is not None:
             out.append(_ptr(phases, torch.float64, "phases"))
         if gains is not None:
@@ -222,18 +250,21 @@ class Stream:
         """Enqueue fe_channelize; ``out`` int8 [A][M/S_h][n][S_h][2][2]."""
         import torch
         a = self._args(raw, n_samples, delays, phases, gains) + [_ptr(out, torch.int8, "out")]
+        check_sizes(self.A, self.n, n_samples, out=out)
         _check(load_library().fe_channelize(*a), "fe_channelize")
 
     def channelize_prequant(self, raw, n_samples: int, delays, phases, gains, y_out):
         """Enqueue fe_channelize_prequant; ``y_out`` float32 [A][2][M][n][2]."""
         import torch
         a = self._args(raw, n_samples, delays, phases, gains) + [_ptr(y_out, torch.float32, "y_out")]
+        check_sizes(self.A, self.n, n_samples, y_out=y_out)
         _check(load_library().fe_channelize_prequant(*a), "fe_channelize_prequant")
 
     def channelize_fir(self, raw, n_samples: int, delays, g_out):
         """Enqueue fe_channelize_fir; ``g_out`` float32 [A][2][M][2n]."""
         import torch
         a = self._args(raw, n_samples, delays) + [_ptr(g_out, torch.float32, "g_out")]
+        check_sizes(self.A, self.n, n_samples, g_out=g_out)
         _check(load_library().fe_channelize_fir(*a), "fe_channelize_fir")
 
 
@@ -242,6 +273,7 @@ class Stream:
         length (0 = per-launch default).  Resets the stream."""
         import torch
         a = self._args(raw, n_samples, delays, phases, gains) + [_ptr(out, torch.int8, "out")]
+        check_sizes(self.A, self.n, n_samples, out=out)
         choice = ctypes.c_int()
         _check(load_library().fe_stream_autotune(*a, int(iters), ctypes.byref(choice)),
                "fe_stream_autotune")
@@ -252,10 +284,10 @@ class Stream:
 
     def _call(self, raw, n_samples, delays, phases, gains, out) -> _Call:
         import torch
-        return _Call(_ptr(raw, torch.uint8, "raw").value, int(n_samples),
-                     _ptr(delays, torch.float64, "delays").value,
-                     _ptr(phases, torch.float64, "phases").value,
-                     _ptr(gains, torch.float32, "gains").value, _ptr(out, torch.int8, "out").value)
+        a = self._args(raw, n_samples, delays, phases, gains)
+        o = _ptr(out, torch.int8, "out")
+        check_sizes(self.A, self.n, n_samples, out=out)
+        return _Call(a[1].value, int(n_samples), a[3].value, a[4].value, a[5].value, o.value)
 
 
 class Batch:

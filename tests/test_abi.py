@@ -130,3 +130,33 @@ def test_missing_library_fails_loudly(tmp_path):
             load_library(str(tmp_path / "nope.so"))
     finally:
         fengine._lib = saved
+
+
+def test_binding_refuses_undersized_buffers():
+    """The binding checks every buffer against the header's layout before any
+    call (an undersized buffer would be read or written past its end)."""
+    import torch
+    from paper_2303_09886_amd.fengine import call_sizes, check_sizes
+    A, n, N = 2, 256, 2 * 256 * 8
+    need = call_sizes(A, n, N)
+    assert need == {"raw": 4 * N * 5 // 4, "delays": 4 * 8, "phases": 4 * 8, "gains": 4 * n * 2,
+                    "out": 4 * N}
+    ok = {"raw": torch.empty(need["raw"], dtype=torch.uint8),
+          "delays": torch.empty(need["delays"], dtype=torch.float64),
+          "phases": torch.empty(need["phases"], dtype=torch.float64),
+          "gains": torch.empty(need["gains"], dtype=torch.float32),
+          "out": torch.empty(need["out"], dtype=torch.int8)}
+    check_sizes(A, n, N, **ok)
+    check_sizes(A, n, N, y_out=torch.empty(4 * N, dtype=torch.float32),
+                g_out=torch.empty(4 * N, dtype=torch.float32))
+    for name in ok:
+        small = dict(ok)
+        small[name] = ok[name][:-1]
+        with pytest.raises(ValueError, match=name):
+            check_sizes(A, n, N, **small)
+    for name in ("y_out", "g_out"):
+        with pytest.raises(ValueError, match=name):
+            check_sizes(A, n, N, **{name: torch.empty(4 * N - 1, dtype=torch.float32)})
+    # a call twice as long needs twice the buffers
+    with pytest.raises(ValueError):
+        check_sizes(A, n, 2 * N, **ok)

@@ -175,6 +175,28 @@ def test_fir_wide_delay_spread(prec):
     assert nw <= FIR_RTOL[prec]
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,T,D,base,M", [(256, 16, 2048, 1500, 1100), (256, 32, 2048, 1900, 1100),
+                                          (1024, 16, 4200, 4100, 600)])
+def test_fir_delays_of_several_rows(prec, n, T, D, base, M):
+    """Coarse delays of several rows (2n samples each), max_delay > 2n: the
+    tiles staged without per-load checks move their row pointer back by whole
+    rows (regression: that path once formed a negative byte offset here)."""
+    _say("mfma fir %s n=%d T=%d max_delay=%d delays ~%d M=%d" % (prec, n, T, D, base, M))
+    shape = synth.Shape(n=n, taps=T, antennas=1, samples=2 * n * M, spectra_per_heap=4)
+    w = synth.make_workload(shape, 41 + n + T)
+    rng = np.random.default_rng(T)
+    F = np.arange(M)
+    w.delays[:] = base + np.floor(F / 97)[None, None, :] + rng.uniform(-0.45, 0.45, size=w.delays.shape)
+    assert w.delays.max() < D
+    g, status = gpu_run(w, w.total, prec, mode="fir", max_delay=D)
+    assert status == fe.FE_OK
+    ref = oracle_run(w, want=("g",), max_delay=D)
+    nw, _ = compare.prequant_errors(g, ref["g"])
+    _say("  g normwise %.3g" % nw)
+    assert nw <= FIR_RTOL[prec]
+
+
 # --------------------------------------------------------------------------
 # Whole path
 # --------------------------------------------------------------------------

@@ -114,6 +114,38 @@ def test_unpack_bit_exact():
         assert np.array_equal(o.cpu().numpy(), x)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_hot_path_unpack_every_code_and_phase(prec):
+    """The unpackers inside the FIR kernels, bit for bit: with one tap of
+    value 1 the filtered sample is the sample itself, g_{F,t} = s_{2nF+t-c_F}
+    (Eq. (1) with T = 1), exactly in every precision (10-bit codes are exact
+    in FP16 and in BF16 hi+lo).  The stream repeats the 1024 codes with
+    period 1025, so every code sits at every bit phase (10 i mod 8); the
+    integer delays step through 0 .. 120 and three calls put the history seam
+    under the first spectra of the later calls."""
+    _say("hot-path unpack %s" % prec)
+    n, S, M, calls = 256, 4, 32, 3
+    shape = synth.Shape(n=n, taps=1, antennas=2, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 11, total=2 * n * M * calls)
+    i = np.arange(w.total)
+    x = np.empty_like(w.x)
+    for a in range(2):
+        for p in range(2):
+            x[a, p] = (i + 257 * (2 * a + p)) % 1025 % 1024 - 512
+    w.x, w.raw = x, synth.pack10(x)
+    w.weights = np.ones_like(w.weights)
+    F = np.arange(M * calls)
+    w.delays[:] = ((F * 7 + 13 * np.arange(4).reshape(2, 2, 1)) % 121).astype(np.float64)
+    st = fe.Stream(n, 1, 2, w.weights, 2 * n * M, spectra_per_heap=S, precision=prec)
+    g, status = gpu_run(w, 2 * n * M, mode="fir", stream=st)
+    st.close()
+    assert status == fe.FE_OK
+    ref = oracle_run(w, want=("g",))
+    assert np.array_equal(g, ref["g"].astype(np.float32))
+    # the window of spectrum F really is the stream shifted by c_F
+    assert np.array_equal(ref["g"][1, 0, 40], x[1, 0, 2 * n * 40 - int(w.delays[1, 0, 40]) + np.arange(2 * n)])
+
+
 # --------------------------------------------------------------------------
 # Steps 1-3a: FIR output with impulses is exact; with noise within 1e-5
 # --------------------------------------------------------------------------
