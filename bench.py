@@ -12,8 +12,12 @@ served from the 256 MB Infinity Cache.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
 Per-kernel durations come from HIP events the library records on its own
-stream, in a second pass after the timed steps.  The CPU baseline times the FP64 oracle on the
-host over the same workload.
+stream around each kernel during the timed steps.  The roofline fraction is
+the path's algorithmic 2.25 bytes per real sample (1.25 B of packed 10-bit
+input, 1 B of int8 output) over the dominant kernel's duration, against the
+8 TB/s HBM peak.  The CPU baseline times the FP64 oracle on the host: on the
+GPU's share of host cores over the whole workload, and on one thread over a
+slice of it.
 """
 from __future__ import annotations
 
@@ -50,62 +54,47 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_figures(shape: synth.Shape, prec: str = "fp32"):
-    """Algorithmic bytes and flops per real input sample of each kernel.
-
-    fir:  reads the packed samples (10 bits) once, writes g: 1.25 B + 4 B
-          (float32; FP16 mode: 2 B); 2T flops (T multiply-adds).
-    post: reads g, writes one int8 (re, im) pair per channel, i.e. 1 B per
-          real sample: 4 B + 1 B (FP16 mode: 2 B + 1 B); n-point complex FFT
-          5 n log2 n / 2n = 2.5 log2 n, real-FFT untangle ~5, phase + gain +
-          quantise ~9 flops.
-    turn: corner turn of the int8 spectra into heaps: 1 B in, 1 B out.
-    """
+def kernel_names(shape: synth.Shape, prec: str, path: str = "split"):
+    """Names of the call's kernels by stage: "fir" is the first kernel (the
+    fused unpack + FIR + FFT + post kernel where the path is fused), "post"
+    the FFT/post kernel of the split path, "turn" the corner turn."""
     n, T = shape.n, shape.taps
-    lg = int(np.log2(n))
-    gb = 2.0 if prec == "fp16" else 4.0
-    return {
-        "fir": {"bytes": 1.25 + gb, "flops": 2.0 * T},
-        "post": {"bytes": gb + 1.0, "flops": 2.5 * lg + 5.0 + 9.0},
-        "turn": {"bytes": 2.0, "flops": 0.0},
-    }
+    if prec == "fp32":
+        tk = next(t for t in (4, 8, 16, 24, 32) if T <= t)
+        if path == "fused":
+            return {"fir": "pfb_fused_kernel<%d,%d>" % (n, tk), "turn": "corner_turn_kernel"}
+        return {"fir": "fir_kernel<%d>" % tk, "post": "fft_post_kernel<%d>" % n, "turn": "corner_turn_kernel"}
+    tk = 16 if T <= 16 else 32
+    return {"fir": "fir_mfma_kernel<%d,%s>" % (tk, prec), "post": "fft_mfma_kernel<%d,%s>" % (n, prec),
+            "turn": "corner_turn_kernel"}
 
 
-KERNEL_NAMES = {
-    "fp32": {"fir": "fir_kernel<%(T)d>", "post": "fft_post_kernel<%(n)d>", "turn": "corner_turn_kernel"},
-    "fp16": {"fir": "fir_mfma_kernel<%(T)d,fp16>", "post": "fft_mfma_kernel<%(n)d,fp16>",
-             "turn": "corner_turn_kernel"},
-    "bf16": {"fir": "fir_mfma_kernel<%(T)d,bf16>", "post": "fft_mfma_kernel<%(n)d,bf16>",
-             "turn": "corner_turn_kernel"},
-}
+def measure(fe, shape, w, sets, dev_arrays, prec, steps, warmup, path="auto"):
+    """Time `steps` channelize calls of one stream at precision `prec`.
 
-
-def measure(fe, shape, w, sets, dev_arrays, prec, steps, warmup):
-    """Time `steps` channelize calls of one stream at precision `prec`; then a
-    second, instrumented pass for the per-kernel durations."""
+    The wall clock around the timed steps gives the headline rate; the
+    library's HIP events, recorded on its own stream around each kernel
+    during the same timed steps, give the per-kernel durations."""
     import torch
     N, A, n = shape.samples, shape.antennas, shape.n
     delays, phases, gains = dev_arrays
     st = fe.Stream(n, shape.taps, A, w.weights, N, spectra_per_heap=shape.spectra_per_heap,
-                   max_delay=shape.max_delay, precision=prec)
-    log("%s: warmup %d steps" % (prec, warmup))
+                   max_delay=shape.max_delay, precision=prec, path=path)
+    path_run = st.schedule()[0]
+    log("%s (%s path): warmup %d steps" % (prec, path_run, warmup))
     for i in range(warmup):
         raw, out = sets[i % len(sets)]
         st.channelize(raw, N, delays, phases, gains, out)
     torch.cuda.synchronize()
     log("%s: timing %d steps" % (prec, steps))
+    st.timing(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         raw, out = sets[i % len(sets)]
         st.channelize(raw, N, delays, phases, gains, out)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # per-kernel durations: a second pass with the library's HIP-event timing
-    # (kept out of the timed steps above)
-    st.timing(True)
-    for i in range(max(1, min(steps, 20))):
-        raw, out = sets[i % len(sets)]
-        st.channelize(raw, N, delays, phases, gains, out)
     fir_ms, post_ms, turn_ms, calls = st.timing_read()
     st.timing(False)
     status = st.status()
@@ -114,26 +103,26 @@ def measure(fe, shape, w, sets, dev_arrays, prec, steps, warmup):
         log("warning: %s stream status %d" % (prec, status))
     ms_step = (t1 - t0) * 1e3 / steps
     samples = A * 2 * N
-    fig = kernel_figures(shape, prec)
-    avg = {"fir": fir_ms / max(calls, 1), "post": post_ms / max(calls, 1),
-           "turn": turn_ms / max(calls, 1)}
+    names = kernel_names(shape, prec, path_run)
+    avg = {"fir": fir_ms / max(calls, 1), "post": post_ms / max(calls, 1), "turn": turn_ms / max(calls, 1)}
+    avg = {k: v for k, v in avg.items() if k in names}
     dom = max(avg, key=avg.get)
-    names = {k: v % {"T": 16 if shape.taps <= 16 else 32, "n": n} if prec != "fp32"
-             else v % {"T": shape.taps, "n": n} for k, v in KERNEL_NAMES[prec].items()}
+    algo = PATH_BYTES_PER_SAMPLE * samples               # algorithmic bytes of one call
     dur_s = avg[dom] * 1e-3
-    achieved = fig[dom]["bytes"] * samples / dur_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": stored_traffic(names[dom]),
-            "kernel": names[dom], "avg_ms": round(avg[dom], 4),
-            "algorithmic_bytes_per_launch": int(fig[dom]["bytes"] * samples)}
-    if prec == "fp32":
-        roof["fp32_tflops"] = round(fig[dom]["flops"] * samples / dur_s / 1e12, 2)
-        roof["fp32_frac_of_peak"] = round(fig[dom]["flops"] * samples / dur_s / 1e12 / FP32_PEAK_TFLOPS, 4)
-    kernels = {names[k]: {"avg_ms": round(avg[k], 4),
-                          "GBps": round(fig[k]["bytes"] * samples / (avg[k] * 1e-3) / 1e9, 1)}
-               for k in avg if avg[k] > 0}
+    achieved = algo / dur_s / 1e9
+    traffic = stored_traffic(names[dom])
     value = samples / (ms_step * 1e-3) / 1e9
-    return {"value": round(value, 2), "ms_per_step": round(ms_step, 4),
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / algo, 3),
+            "kernel": names[dom], "avg_ms": round(avg[dom], 4), "algorithmic_bytes_per_launch": int(algo),
+            "basis": "2.25 B per real input sample (1.25 B packed 10-bit in, 1 B int8 out) x %d samples "
+                     "per launch / the kernel's average duration" % samples,
+            "call": {"achieved": round(value * PATH_BYTES_PER_SAMPLE, 1),
+                     "frac": round(value * PATH_BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4)}}
+    kernels = {names[k]: {"avg_ms": round(avg[k], 4), "share_of_call": round(avg[k] / ms_step, 3)}
+               for k in avg if avg[k] > 0}
+    return {"value": round(value, 2), "ms_per_step": round(ms_step, 4), "path": path_run,
             "hbm_roofline_frac": round(value * PATH_BYTES_PER_SAMPLE / HBM_PEAK_GBS, 4),
             "roofline": roof, "kernels": kernels}
 
@@ -270,17 +259,28 @@ def measure_service(chunks: int = 24, seed: int = 3):
     return res
 
 
-def cpu_baseline(w: synth.Workload, spectra: int, threads: int, min_seconds: float = 10.0):
-    """Time the FP64 oracle on spectra [0, spectra) of every antenna, split
-    over a thread pool (ctypes releases the GIL); the pass is repeated until
-    at least `min_seconds` of wall time have been measured."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w: synth.Workload, antennas: int, spectra: int, threads: int, min_seconds: float = 10.0):
+    """Time the FP64 oracle on spectra [0, spectra) of the first `antennas`
+    antennas (both pols), split over `threads` threads (ctypes releases the
+    GIL); the pass is repeated until at least `min_seconds` of wall time have
+    been measured.  The rate is channelized real samples per second."""
     import oracle
     oracle.lib()
     s = w.shape
-    A = s.antennas
-    per = max(1, -(-spectra * A // threads))
+    per = max(1, -(-spectra * antennas // threads))
     tasks = []
-    for a in range(A):
+    for a in range(antennas):
         for f0 in range(0, spectra, per):
             tasks.append((a, f0, min(spectra, f0 + per)))
 
@@ -298,13 +298,45 @@ def cpu_baseline(w: synth.Workload, spectra: int, threads: int, min_seconds: flo
             samples += sum(ex.map(run, tasks))
             passes += 1
             dt = time.perf_counter() - t0
-            if dt >= min_seconds or passes >= 50:
+            if dt >= min_seconds or passes >= 200:
                 break
     return {"value": samples / dt / 1e9, "unit": "Gsample/s", "cores": threads, "kind": "oracle",
-            "sample": "%d pass(es) over spectra 0..%d of all %d antennas x 2 pols of the benchmark "
-                      "workload (%d samples in all), FP64 C oracle, %d threads"
-                      % (passes, spectra - 1, A, samples, threads),
-            "seconds": dt}
+            "sample": "%d pass(es) over spectra 0..%d of antennas 0..%d (both pols) of the benchmark "
+                      "workload, %d samples in all, FP64 C oracle, %d thread(s)"
+                      % (passes, spectra - 1, antennas - 1, samples, threads),
+            "seconds": round(dt, 2)}
+
+
+def measure_small(fe, steps: int, warmup: int):
+    """The small workload (1 antenna x 2 pols x 2^20 samples, 1024 channels,
+    16 taps): time per call (launch-bound at this size) and its rate."""
+    import torch
+    sh = synth.SMALL
+    w = synth.make_workload(sh, 1)
+    M = sh.samples // (2 * sh.n)
+    st = fe.Stream(sh.n, sh.taps, sh.antennas, w.weights, sh.samples, spectra_per_heap=sh.spectra_per_heap,
+                   max_delay=sh.max_delay)
+    args = [torch.from_numpy(a).cuda() for a in (w.raw, w.delays, w.phases, w.gains)]
+    out = torch.empty((sh.antennas, M // sh.spectra_per_heap, sh.n, sh.spectra_per_heap, 2, 2),
+                      dtype=torch.int8, device="cuda")
+    for _ in range(warmup):
+        st.channelize(args[0], sh.samples, args[1], args[2], args[3], out)
+    torch.cuda.synchronize()
+    st.timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.channelize(args[0], sh.samples, args[1], args[2], args[3], out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    fir_ms, post_ms, turn_ms, calls = st.timing_read()
+    st.timing(False)
+    st.close()
+    samples = sh.antennas * 2 * sh.samples
+    return {"ms_per_call": round(ms, 4), "value": round(samples / (ms * 1e-3) / 1e9, 2), "unit": "Gsample/s",
+            "kernel_ms": round((fir_ms + post_ms + turn_ms) / max(calls, 1), 4),
+            "config": "1 antenna x 2 pols, 2^20 samples/pol per call, 1024 channels, 16 taps, heaps of 256 "
+                      "spectra (the parity workload; its 4.7 MB move in under a microsecond at the HBM "
+                      "peak, so the call time is launch latency)"}
 
 
 def main():
@@ -316,8 +348,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=None,
                     help="spectra per antenna for the CPU baseline (default: all)")
-    ap.add_argument("--variants", default="fp16,bf16",
-                    help="matrix-core variants timed beside the FP32 path (comma list, '' for none)")
+    ap.add_argument("--variants", default="fp16,bf16,fused",
+                    help="variants timed beside the FP32 path: fp16, bf16 (matrix cores), fused "
+                         "(the FP32 stream on the fused kernel); comma list, empty for none")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-stream batch measurement")
     ap.add_argument("--no-service", action="store_true", help="skip the streaming-service measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -360,6 +393,11 @@ def main():
     res = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup)
     variants = {}
     for prec in args.variants.split(",") if args.variants else []:
+        if prec == "fused":
+            # the same FP32 stream on the fused kernel (fe_stream_set_schedule)
+            variants["fp32_fused"] = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup,
+                                             path="fused")
+            continue
         r = measure(fe, shape, w, sets, dev_arrays, prec, args.steps, args.warmup)
         variants[prec + "_mfma"] = r
 
@@ -383,12 +421,22 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    small = measure_small(fe, max(20, args.steps), args.warmup)
+
     cpu = None
     if not args.no_cpu_baseline:
-        threads = min(16, len(os.sched_getaffinity(0)))
+        # the host share of one GPU on these boxes is 16 cores, whatever the
+        # machine shows; the single-thread run times a bounded slice
+        visible = len(os.sched_getaffinity(0))
+        threads = min(16, visible)
         spectra = M if args.cpu_spectra is None else args.cpu_spectra
         log("cpu baseline: oracle over %d spectra x %d antennas, %d threads" % (spectra, A, threads))
-        cpu = cpu_baseline(w, spectra, threads)
+        cpu = cpu_baseline(w, A, spectra, threads)
+        log("cpu baseline: 1 thread over 96 spectra x 1 antenna")
+        one = cpu_baseline(w, 1, min(96, M), 1)
+        cpu["single_thread"] = {k: one[k] for k in ("value", "unit", "cores", "sample", "seconds")}
+        cpu["cpu_model"] = cpu_model()
+        cpu["host_cpus_visible"] = visible
 
     rec = {
         "metric": METRIC,
@@ -409,6 +457,7 @@ def main():
                    "antennas": A, "pols": 2, "samples_per_pol": N, "channels": n,
                    "taps": shape.taps, "spectra_per_heap": S, "max_delay": shape.max_delay,
                    "buffer_sets": args.sets},
+        "small_workload": small,
         "hbm_roofline_frac": res["hbm_roofline_frac"],
         "roofline": res["roofline"],
         "kernels": res["kernels"],

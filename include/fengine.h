@@ -180,8 +180,9 @@ fe_status fe_debug_unpack10(const uint8_t *raw, int64_t first, int64_t count,
 
 /* Time the stream's launch choices on the caller's buffers (an fe_channelize
  * call's arguments; `iters` timed calls per candidate, HIP events on the
- * stream's HIP stream) and keep the fastest.  The candidates set the FIR's
- * schedule: for FP32 streams its run length -- how many consecutive batches
+ * stream's HIP stream) and keep the fastest.  Where the stream can run both
+ * paths (fe_stream_set_schedule) each is timed, and the faster kept.  The
+ * candidates set the FIR's schedule: for FP32 streams its run length -- how many consecutive batches
  * of spectra one workgroup filters (a batch is 64 spectra, 48 for 24 taps),
  * trading tap reloads against parallelism; for FP16/BF16 streams the chain
  * length of the matrix-core FIR -- how many consecutive 256-spectrum tiles
@@ -199,6 +200,30 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
  * batches of spectra per run (FP32) or tiles per chain (FP16/BF16), as
  * above). */
 fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches);
+
+/* Kernels of the path (fe_stream_set_schedule). */
+enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2 };
+
+/* Choose the kernels that run a stream's calls, and the FIR schedule.
+ * FE_PATH_SPLIT: a FIR kernel (steps 1-3a) writes the filtered samples as
+ *   float32 to the stream's workspace, an FFT/post-processing kernel
+ *   (steps 3b-6) reads them back, a corner-turn kernel writes the heaps.
+ * FE_PATH_FUSED (FP32 streams with n <= 4096 and T <= 16 only): one kernel
+ *   filters four consecutive spectra of a polarization into on-chip memory
+ *   and transforms and finishes them there; no filtered sample is written to
+ *   device memory.  Then the corner turn.
+ * FE_PATH_AUTO: fused for T <= 8 and n <= 2048, else split (the faster of the
+ *   two on MI355X for those shapes).
+ * Streams the fused path cannot run always run the split path (the setting
+ * is kept).  fir_batches as in fe_stream_set_tuning; on the fused path it
+ * caps the kernel's workgroups per compute unit (0 = as many as fit).
+ * fe_stream_autotune chooses both.  FE_EINVAL for an unknown path or
+ * fir_batches outside 0..64. */
+fe_status fe_stream_set_schedule(fe_stream *s, int path, int fir_batches);
+
+/* The path the stream's calls run now (FE_PATH_SPLIT or FE_PATH_FUSED) and
+ * its fir_batches setting.  Either pointer may be NULL. */
+fe_status fe_stream_get_schedule(const fe_stream *s, int *path, int *fir_batches);
 
 /* ---- Batches of streams ------------------------------------------------ */
 

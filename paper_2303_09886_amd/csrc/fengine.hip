@@ -724,6 +724,250 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
 }
 
 // ---------------------------------------------------------------------------
+// Kernel 1F (n <= 4096, FP32): the whole path of one stream in one kernel --
+// unpack, coarse delay and the FIR of Eq. (1) straight into LDS, then the
+// n-point complex FFT there, the untangle, phase, gain and quantisation of
+// kernel 2.  No filtered sample leaves the workgroup.
+//
+// Workgroup = one stream (antenna, pol) and a run of steps of PF_S = 4
+// consecutive spectra F0 .. F0+3.  Thread b (of n/4) owns the column pairs
+// m = b + (n/4) q, q < 4 (z[m] = g[2m] + i g[2m+1]) of all four spectra.
+// When the step's spectra share one coarse delay c, they read rows
+// F0-T+1 .. F0+3 of those columns at offset -c, so each loaded pair of
+// samples serves up to four outputs (T + 3 rows for 4 T products per
+// column), and each column's taps, read from L2 once per step, serve the four
+// spectra.  A pair of samples (20 bits) lies in the 4 bytes from byte
+// floor(5 i / 4) of its first sample i: one unaligned dword load, a byte
+// swap, two sign-extending bitfield extracts.  Steps whose spectra differ in
+// delay, read rows before the call (the history seam) or have an invalid
+// delay take a per-spectrum path.  The four spectra's z go to four LDS
+// buffers; thread groups of n/16 then transform one spectrum each (radix-16
+// Stockham passes) and finish its channels.
+// ---------------------------------------------------------------------------
+
+constexpr int PF_S = 4;                     // spectra per step
+
+enum { OUT_G = 2 };                         // (besides OUT_INT8, OUT_PREQUANT) the FIR output g
+
+typedef uint32_t __attribute__((aligned(1))) u32_unaligned;
+
+// unaligned 32-bit global load at byte `off` of a wave-uniform base
+__device__ __forceinline__ uint32_t load_u32u(gptr8 base, uint32_t off)
+{
+    return *reinterpret_cast<const u32_unaligned __attribute__((address_space(1))) *>(base + off);
+}
+
+// Radix-16 Stockham pass with L = 1 (no twiddles) over one polarization's n
+// points in LDS: butterfly b reads z[b + q n/16], writes 16 b + r.
+template <int N>
+__device__ __forceinline__ void fft_pass0(float2 *__restrict__ buf, int tp)
+{
+    constexpr int NB = N / 16;
+    float2 v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = buf[lds_pad(tp + q * NB)];
+    __syncthreads();
+    Dft<16>::run(v);
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        buf[lds_pad(tp * 16 + r)] = v[r];
+    __syncthreads();
+}
+
+// taps (h[2m + 2n j], h[2m + 1 + 2n j]), j < T, of column pair m: a scalar
+// row pointer plus one lane offset per load
+template <int T, int N2>
+__device__ __forceinline__ void load_tap_pairs(float2 (&h)[T], const float *taps, int m)
+{
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    typedef const v2f __attribute__((address_space(1))) *gptr_v2f;
+    gptr8 tb = (gptr8)taps;
+    const uint32_t off = uint32_t(m) * 8u;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        asm volatile("" : "+s"(tb));
+        const v2f v = *reinterpret_cast<gptr_v2f>(tb + off);
+        h[j] = make_float2(v.x, v.y);
+        tb += N2 * 4;
+    }
+}
+
+template <int N, int T, int MODE>
+__global__ __launch_bounds__(N / 4) void pfb_fused_kernel(
+    const uint8_t *__restrict__ raw, int64_t raw_stride,
+    const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
+    const float *__restrict__ taps, const double *__restrict__ delays,
+    const double *__restrict__ phases, const float2 *__restrict__ gains,
+    const float2 *__restrict__ tw_all, const float2 *__restrict__ untangle,
+    uint32_t *__restrict__ spec8, float2 *__restrict__ y_out, float2 *__restrict__ g_out,
+    int *__restrict__ status, int M, int D, int streams, int mb, int me)
+{
+    static_assert(Plan<N>::R[0] == 16, "plans start with a radix-16 pass");
+    constexpr int NT = N / 4;               // threads: 4 column pairs each
+    constexpr int NTP = N / 16;             // threads per spectrum in the FFT
+    constexpr int NH = N / 64;
+    constexpr int n2 = 2 * N;
+    constexpr int row_bytes = n2 / 4 * 5;   // 2n packed samples
+    constexpr int NR = T + PF_S - 1;        // rows of a step
+    __shared__ float2 buf[PF_S][lds_len<N>()];
+    __shared__ float2 ph_hi[PF_S][NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[PF_S][64];
+
+    // Work units (stream, step) in stream-major order are split into eight
+    // contiguous ranges, one per XCD (workgroup b runs on XCD b mod 8; the
+    // grid is a multiple of 8).  The K workgroups of an XCD interleave their
+    // range's steps (unit u0 + k, u0 + k + K, ...), so that at any time they
+    // work on neighbouring steps of a stream and share its rows and the taps
+    // in their L2.
+    const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3, K = gridDim.x >> 3;
+    const int nsteps = (me - mb + PF_S - 1) / PF_S;
+    const int64_t units = int64_t(streams) * nsteps;
+    const int64_t u_begin = units * xcd / 8, u_end = units * (xcd + 1) / 8;
+    const int tid = threadIdx.x;
+
+    for (int64_t u = u_begin + k; u < u_end; u += K) {
+        const int s = int(u / nsteps);                    // stream = 2 a + p
+        const int step = int(u - int64_t(s) * nsteps);
+        const int F0 = mb + PF_S * step;
+        const uint8_t *rs = raw + int64_t(s) * raw_stride;
+        const double *ds = delays + int64_t(s) * M;
+        // lane values are derived afresh each step (hoisted out of the step
+        // loop, their 64-bit addresses would not fit the registers)
+        int ltid = tid;
+        asm volatile("" : "+v"(ltid));
+        const int fg = ltid / NTP, tp = ltid % NTP;
+        // the step's delays (the same in every lane)
+        int cf[PF_S];
+        double tauf[PF_S];
+        bool okf[PF_S], live[PF_S];
+#pragma unroll
+        for (int f = 0; f < PF_S; ++f) {
+            live[f] = F0 + f < me;
+            okf[f] = live[f] && split_delay(ds[F0 + f], D, cf[f], tauf[f]);
+        }
+        if (tid == 0) {
+#pragma unroll
+            for (int f = 0; f < PF_S; ++f)
+                if (live[f] && !okf[f])
+                    atomicOr(status, 1);
+        }
+        if (MODE != OUT_G && live[fg])
+            phase_tables<N, NTP>(ph_hi[fg], ph_lo[fg], phases[int64_t(s) * M + F0 + fg], tauf[fg], 0.5f, tp);
+
+        const int c = cf[0];
+        bool fast = okf[0] && okf[1] && okf[2] && okf[3] && cf[1] == c && cf[2] == c && cf[3] == c
+                    && int64_t(n2) * (F0 - T + 1) - c >= 0;
+        if (fast) {
+            // rows F0-T+1 .. F0+3 at delay c: c = 2n cr + cc, so the rows start
+            // cr rows earlier and lane offsets keep cc (plus one row of
+            // margin, so that they are never negative)
+            const int cr = c / n2, cc = c - cr * n2;
+            const gptr8 rp0 = (gptr8)rs + int64_t(F0 - T + 1 - cr - 1) * row_bytes;
+            // the call's last row: a pair that does not need the fourth byte
+            // from its first is read from one byte earlier, so that no load
+            // passes the end of the chunk
+            const bool tail = F0 + PF_S - 1 - cr == M - 1;
+            auto lane_geo = [&](int q, uint32_t &off, uint32_t &lo0, uint32_t &shl) {
+                const int u2 = 2 * (ltid + NT * q) - cc;          // first sample of the pair in its row
+                const uint32_t ua = uint32_t(u2) & 3u;
+                off = uint32_t(row_bytes + ((5 * u2) >> 2));
+                lo0 = 22u - 2u * ua;                              // bit position of the first sample
+                shl = tail && ua != 3u ? 1u : 0u;
+            };
+            auto load_rows = [&](int q, uint32_t (&w)[NR]) {
+                uint32_t off, lo0, shl;
+                lane_geo(q, off, lo0, shl);
+                gptr8 rp = rp0;
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    asm volatile("" : "+s"(rp));
+                    w[r] = load_u32u(rp, r == NR - 1 ? off - shl : off);
+                    rp += row_bytes;
+                }
+            };
+            // the rows of pair q + 1 are loaded while pair q is filtered
+            uint32_t wn[NR];
+            load_rows(0, wn);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = ltid + NT * q;
+                uint32_t w[NR];
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+                    w[r] = wn[r];
+                if (q + 1 < 4)
+                    load_rows(q + 1, wn);
+                float2 h[T];
+                load_tap_pairs<T, n2>(h, taps, m);
+                uint32_t off, lo0, shl;
+                lane_geo(q, off, lo0, shl);
+                float x0[NR], x1[NR];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const uint32_t lo = r == NR - 1 ? lo0 - 8u * shl : lo0;
+                    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, w[r], 0x00010203u));
+                    x0[r] = float(int32_t(__builtin_amdgcn_sbfe(be, lo, 10u)));
+                    x1[r] = float(int32_t(__builtin_amdgcn_sbfe(be, lo - 10u, 10u)));
+                }
+#pragma unroll
+                for (int f = 0; f < PF_S; ++f) {
+                    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+                    for (int j = 0; j < T; ++j) {
+                        a0 = fmaf(x0[f + j], h[j].x, a0);
+                        a1 = fmaf(x1[f + j], h[j].y, a1);
+                    }
+                    if (MODE == OUT_G)
+                        g_out[(int64_t(s) * M + F0 + f) * N + m] = make_float2(a0, a1);
+                    else
+                        buf[f][lds_pad(m)] = make_float2(a0, a1);
+                }
+            }
+        } else {
+            // per spectrum: its own delay, rows before the call from the
+            // history, invalid delays and spectra past the launch as zeros
+            const uint8_t *hs = hist + int64_t(s) * hist_stride;
+#pragma unroll 1
+            for (int q = 0; q < 4; ++q) {
+                const int m = ltid + NT * q;
+                float2 h[T];
+                load_tap_pairs<T, n2>(h, taps, m);
+#pragma unroll 1
+                for (int f = 0; f < PF_S; ++f) {
+                    float a0 = 0.f, a1 = 0.f;
+                    if (okf[f]) {
+                        int64_t i = int64_t(n2) * (F0 + f - T + 1) + 2 * m - cf[f];
+#pragma unroll
+                        for (int j = 0; j < T; ++j) {
+                            a0 = fmaf(float(sample_at(rs, hs, i, H)), h[j].x, a0);
+                            a1 = fmaf(float(sample_at(rs, hs, i + 1, H)), h[j].y, a1);
+                            i += n2;
+                        }
+                    }
+                    if (MODE == OUT_G) {
+                        if (live[f])
+                            g_out[(int64_t(s) * M + F0 + f) * N + m] = make_float2(a0, a1);
+                    } else {
+                        buf[f][lds_pad(m)] = make_float2(a0, a1);
+                    }
+                }
+            }
+        }
+        if (MODE == OUT_G)
+            continue;
+        __syncthreads();
+        // FFT of spectrum fg by threads tp < n/16, then its channels
+        fft_pass0<N>(buf[fg], tp);
+        fft_rest<N, 1>(buf[fg], tp, tw_all);
+        if (live[fg])
+            post_spectrum<N, NTP, MODE>(buf[fg], ph_hi[fg], ph_lo[fg], untangle, gains + int64_t(s) * N,
+                                        okf[fg], int64_t(s) * M + F0 + fg, tp, spec8, y_out);
+        __syncthreads();                    // the buffers and tables are refilled next step
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Channel counts above what one workgroup's LDS holds (n = 16384, 32768):
 // the FFT in two levels (the decomposition behind the paper's Sec. 4 "unzip",
 // here with 16 as the first factor).
@@ -1765,10 +2009,12 @@ struct fe_stream {
     int prec;               // FE_PREC_*
     int fir_batches;        // FIR schedule: run length in batches of spectra (FP32) or
                             // tiles per chain (matrix-core FIR); 0: chosen per launch
+    int path;               // FE_PATH_*: split or fused kernels (FP32, n <= 4096, T <= 16)
     float tap_scale;        // FP16 mode: taps scaled by 2^sc on the matrix cores
     float out_scale;        // 2^-sc, applied to the FIR's FP32 result
     int64_t max_samples;
     int device;
+    int cus;                // compute units of the device
     hipStream_t stream;
     float *d_taps;          // [2n*Tk], zero-padded in front when Tk > T
     float2 *d_tw;           // FFT twiddle blocks
@@ -2111,6 +2357,89 @@ void launch_post(const fe_stream *s, int M, const double *delays, const double *
     }
 }
 
+// The fused path (pfb_fused_kernel) can run FP32 streams with n <= 4096 and
+// at most 16 (kernel) taps.  Chosen by default where it measured faster on
+// MI355X than the split path (FIR kernel, g in device memory, FFT/post
+// kernel): 8 taps or fewer and n <= 2048.  With 16 taps the fused kernel's
+// FIR reloads every tap and re-unpacks T + 3 rows for each step of four
+// spectra, where the split FIR keeps taps and a sliding window in registers.
+bool fused_eligible(const fe_stream *s)
+{
+    return s->prec == FE_PREC_FP32 && s->n <= 4096 && s->Tk <= 16;
+}
+
+bool fused_path(const fe_stream *s)
+{
+    if (!fused_eligible(s) || s->path == FE_PATH_SPLIT)
+        return false;
+    return s->path == FE_PATH_FUSED || (s->Tk <= 8 && s->n <= 2048);
+}
+
+// Workgroups of the fused kernel: a multiple of 8 (one share per XCD), at
+// most what the GPU holds at once (s->fir_batches, when tuned, sets the
+// workgroups per CU), never more than the work units.
+unsigned fused_blocks(const fe_stream *s, int n, int64_t units)
+{
+    // resident workgroups per CU: LDS (4 spectra of n + n/16 complex values
+    // and their phase tables) and at most 2048 threads per CU
+    const int64_t lds = int64_t(PF_S) * (n + n / 16) * 8 + int64_t(PF_S) * (std::max(n / 64, 1) + 64) * 8;
+    int per_cu = int(std::min<int64_t>(160 * 1024 / lds, 2048 / (n / 4)));
+    if (s->fir_batches > 0)
+        per_cu = std::min(per_cu, s->fir_batches);
+    int64_t b = int64_t(std::max(per_cu, 1)) * s->cus;
+    b = std::min<int64_t>(b, (units + 7) / 8 * 8);
+    return unsigned(std::max<int64_t>(8, b / 8 * 8));
+}
+
+template <int N, int T>
+void launch_fused_NT(const fe_stream *s, const uint8_t *raw, int64_t Ns, const double *delays,
+                     const double *phases, const float *gains, float *y_out, float *g_out, int mb, int me)
+{
+    const int M = int(Ns / (2 * N));
+    const int nsteps = (me - mb + PF_S - 1) / PF_S;
+    const int streams = 2 * s->A;
+    const unsigned blocks = fused_blocks(s, N, int64_t(streams) * nsteps);
+    const float2 *gn = reinterpret_cast<const float2 *>(gains);
+    float2 *y2 = reinterpret_cast<float2 *>(y_out);
+    float2 *g2 = reinterpret_cast<float2 *>(g_out);
+    const int64_t rstride = Ns * 5 / 4, hstride = int64_t(s->H) * 5 / 4;
+    if (g_out)
+        hipLaunchKernelGGL((pfb_fused_kernel<N, T, OUT_G>), dim3(blocks), dim3(N / 4), 0, s->stream,
+                           raw, rstride, s->d_hist, hstride, s->H, s->d_taps, delays, phases, gn, s->d_tw,
+                           s->d_untangle, s->d_spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
+    else if (y_out)
+        hipLaunchKernelGGL((pfb_fused_kernel<N, T, OUT_PREQUANT>), dim3(blocks), dim3(N / 4), 0, s->stream,
+                           raw, rstride, s->d_hist, hstride, s->H, s->d_taps, delays, phases, gn, s->d_tw,
+                           s->d_untangle, s->d_spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
+    else
+        hipLaunchKernelGGL((pfb_fused_kernel<N, T, OUT_INT8>), dim3(blocks), dim3(N / 4), 0, s->stream,
+                           raw, rstride, s->d_hist, hstride, s->H, s->d_taps, delays, phases, gn, s->d_tw,
+                           s->d_untangle, s->d_spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
+}
+
+template <int N>
+void launch_fused_N(const fe_stream *s, const uint8_t *raw, int64_t Ns, const double *delays,
+                    const double *phases, const float *gains, float *y_out, float *g_out, int mb, int me)
+{
+    switch (s->Tk) {
+    case 4: launch_fused_NT<N, 4>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 8: launch_fused_NT<N, 8>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 16: launch_fused_NT<N, 16>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    }
+}
+
+void launch_fused(const fe_stream *s, const uint8_t *raw, int64_t Ns, const double *delays,
+                  const double *phases, const float *gains, float *y_out, float *g_out, int mb, int me)
+{
+    switch (s->n) {
+    case 256: launch_fused_N<256>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 512: launch_fused_N<512>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 1024: launch_fused_N<1024>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 2048: launch_fused_N<2048>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 4096: launch_fused_N<4096>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    }
+}
+
 void launch_corner_turn(const fe_stream *s, int M, int8_t *out)
 {
     const int ftiles = (M + CT - 1) / CT, ktiles = s->n / CT;
@@ -2186,11 +2515,15 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
             (void)hipEventRecord(ev[i], s->stream);
     };
     mark(0);
-    launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g, 0, M, g_out != nullptr);
+    const bool fused = fused_path(s);
+    if (fused)
+        launch_fused(s, raw, N, delays, phases, gains, y_out, g_out, 0, M);
+    else
+        launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g, 0, M, g_out != nullptr);
     mark(1);
     launch_history_update(s, raw, N);
     mark(2);
-    if (!g_out)
+    if (!g_out && !fused)
         launch_post(s, M, delays, phases, gains, y_out, 0, M);
     mark(3);
     if (!g_out && !y_out)
@@ -2259,6 +2592,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     s->T = T;
     s->prec = cfg->precision;
     s->fir_batches = 0;
+    s->path = FE_PATH_AUTO;
     s->Tk = s->prec == FE_PREC_FP32 ? kernel_taps(T) : kernel_taps_mfma(T);
     s->tap_scale = s->out_scale = 1.f;
     if (s->prec == FE_PREC_FP16) {
@@ -2284,10 +2618,12 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     int64_t H = int64_t(2) * n * (s->Tk - 1) + s->D;
     H = (H + 15) / 16 * 16;                   // whole dwords of packed samples
     s->H = int(H);
-    if (hipGetDevice(&s->device) != hipSuccess) {
+    if (hipGetDevice(&s->device) != hipSuccess
+        || hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) {
         delete s;
         return FE_EHIP;
     }
+    s->cus = std::max(s->cus, 8);
 
     const int streams = 2 * s->A;
     const int64_t n2 = 2 * int64_t(n);
@@ -2524,22 +2860,27 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
     // per-launch choice; each timed with HIP events over `iters` calls
     // FIR run length in batches of spectra (FP32), or spectrum tiles per
     // workgroup chain (matrix-core FIR); 0 = the per-launch default
+    // (fused path: workgroups per CU, same candidates), for each of the paths
+    // the stream can run
     static const int cand[] = {0, 1, 2, 4, 8};
     const int ncand = 5;
+    const int paths[2] = {FE_PATH_SPLIT, FE_PATH_FUSED};
+    const int npaths = fused_eligible(s) ? 2 : 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0)
             (void)hipEventDestroy(e0);
         return FE_EHIP;
     }
-    const int saved = s->fir_batches;
+    const int saved = s->fir_batches, saved_path = s->path;
     const bool timing = s->timing;
     s->timing = false;
     float best_ms = 3.0e38f;
-    int best = 0;
+    int best = 0, best_path = saved_path;
     st = FE_OK;
-    for (int c = 0; c < ncand && st == FE_OK; ++c) {
-        s->fir_batches = cand[c];
+    for (int c = 0; c < ncand * npaths && st == FE_OK; ++c) {
+        s->path = npaths > 1 ? paths[c / ncand] : saved_path;
+        s->fir_batches = cand[c % ncand];
         st = channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr);   // warm
         if (st != FE_OK)
             break;
@@ -2555,13 +2896,15 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best_ms) {
             best_ms = ms;
-            best = cand[c];
+            best = cand[c % ncand];
+            best_path = s->path;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     s->timing = timing;
     s->fir_batches = st == FE_OK ? best : saved;
+    s->path = st == FE_OK ? best_path : saved_path;
     if (choice)
         *choice = s->fir_batches;
     // the timing calls advanced the stream like real calls: restart it
@@ -2575,6 +2918,27 @@ fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches)
     if (!s || fir_batches < 0 || fir_batches > 64)
         return FE_EINVAL;
     s->fir_batches = fir_batches;
+    return FE_OK;
+}
+
+fe_status fe_stream_set_schedule(fe_stream *s, int path, int fir_batches)
+{
+    if (!s || fir_batches < 0 || fir_batches > 64
+        || (path != FE_PATH_AUTO && path != FE_PATH_SPLIT && path != FE_PATH_FUSED))
+        return FE_EINVAL;
+    s->path = path;
+    s->fir_batches = fir_batches;
+    return FE_OK;
+}
+
+fe_status fe_stream_get_schedule(const fe_stream *s, int *path, int *fir_batches)
+{
+    if (!s)
+        return FE_EINVAL;
+    if (path)
+        *path = fused_path(s) ? FE_PATH_FUSED : FE_PATH_SPLIT;
+    if (fir_batches)
+        *fir_batches = s->fir_batches;
     return FE_OK;
 }
 

@@ -17,6 +17,8 @@ from . import build as _build
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EHIP, FE_EDELAY, FE_ESIZE = 0, -1, -2, -3, -4, -5
 FE_PREC_FP32, FE_PREC_FP16, FE_PREC_BF16 = 0, 1, 2
 PRECISIONS = {"fp32": FE_PREC_FP32, "fp16": FE_PREC_FP16, "bf16": FE_PREC_BF16}
+FE_PATH_AUTO, FE_PATH_SPLIT, FE_PATH_FUSED = 0, 1, 2
+PATHS = {"auto": FE_PATH_AUTO, "split": FE_PATH_SPLIT, "fused": FE_PATH_FUSED}
 
 
 class FEngineError(RuntimeError):
@@ -80,6 +82,10 @@ def load_library(path: Optional[str] = None):
     L.fe_stream_autotune.restype = _st
     L.fe_stream_set_tuning.argtypes = [_vp, ctypes.c_int]
     L.fe_stream_set_tuning.restype = _st
+    L.fe_stream_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
+    L.fe_stream_set_schedule.restype = _st
+    L.fe_stream_get_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    L.fe_stream_get_schedule.restype = _st
     L.fe_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp, ctypes.POINTER(_vp)]
     L.fe_batch_create.restype = _st
     L.fe_batch_destroy.argtypes = [_vp]
@@ -167,13 +173,14 @@ class Stream:
 
     ``weights`` is a host float32 array of 2n*T taps (copied at creation).
     ``precision`` is "fp32" (default), "fp16" or "bf16" (the matrix-core
-    variants of the FIR and FFT, FE_PREC_* in the header).
+    variants of the FIR and FFT, FE_PREC_* in the header).  ``path`` is
+    "auto" (default), "split" or "fused" (fe_stream_set_schedule).
     Work is enqueued on ``hip_stream`` (default: torch's current stream).
     """
 
     def __init__(self, n_channels: int, taps: int, n_antennas: int, weights,
                  max_samples: int, spectra_per_heap: int = 256, max_delay: int = 128,
-                 hip_stream=None, precision="fp32"):
+                 hip_stream=None, precision="fp32", path="auto"):
         import numpy as np
         L = load_library()
         w = np.ascontiguousarray(weights, dtype=np.float32)
@@ -187,6 +194,8 @@ class Stream:
         _check(L.fe_stream_create(ctypes.byref(cfg), _hip_stream(hip_stream), ctypes.byref(h)),
                "fe_stream_create")
         self._h = h
+        if path != "auto":
+            self.set_schedule(path, 0)
         self.n, self.taps, self.A = n_channels, taps, n_antennas
         self.precision = prec
         self.S, self.max_delay, self.max_samples = spectra_per_heap, max_delay, max_samples
@@ -281,6 +290,18 @@ class Stream:
 
     def set_tuning(self, fir_batches: int):
         _check(load_library().fe_stream_set_tuning(self._h, int(fir_batches)), "fe_stream_set_tuning")
+
+    def set_schedule(self, path, fir_batches: int = 0):
+        """fe_stream_set_schedule; ``path`` "auto", "split", "fused" or FE_PATH_*."""
+        p = PATHS[path] if isinstance(path, str) else int(path)
+        _check(load_library().fe_stream_set_schedule(self._h, p, int(fir_batches)), "fe_stream_set_schedule")
+
+    def schedule(self):
+        """(path that runs: "split" or "fused", fir_batches)."""
+        p, b = ctypes.c_int(), ctypes.c_int()
+        _check(load_library().fe_stream_get_schedule(self._h, ctypes.byref(p), ctypes.byref(b)),
+               "fe_stream_get_schedule")
+        return ("fused" if p.value == FE_PATH_FUSED else "split"), int(b.value)
 
     def _call(self, raw, n_samples, delays, phases, gains, out) -> _Call:
         import torch

@@ -112,6 +112,8 @@ def test_batch_and_tuning_reject_bad_arguments(lib):
     dummy = ctypes.c_void_p(0x1000)
     assert lib.fe_stream_autotune(None, dummy, 1 << 20, dummy, dummy, dummy, dummy, 1, None) == fe.FE_EINVAL
     assert lib.fe_stream_set_tuning(None, 1) == fe.FE_EINVAL
+    assert lib.fe_stream_set_schedule(None, fe.FE_PATH_FUSED, 0) == fe.FE_EINVAL
+    assert lib.fe_stream_get_schedule(None, None, None) == fe.FE_EINVAL
     assert ctypes.sizeof(fengine._Call) == 48
 
 

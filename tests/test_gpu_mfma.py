@@ -192,8 +192,16 @@ def test_fir_delays_of_several_rows(prec, n, T, D, base, M):
     g, status = gpu_run(w, w.total, prec, mode="fir", max_delay=D)
     assert status == fe.FE_OK
     ref = oracle_run(w, want=("g",), max_delay=D)
-    nw, _ = compare.prequant_errors(g, ref["g"])
-    _say("  g normwise %.3g" % nw)
+    # The first spectra's windows hold only the stream's first few dozen
+    # samples under the window's smallest taps: their FIR values (~1e-5) lie
+    # in FP16's subnormal range (below 2^-14), where FP16 keeps an absolute,
+    # not a relative, precision.  Each spectrum's error is therefore measured
+    # against its own norm or 1% of the median spectrum norm, whichever is
+    # larger; a misplaced row or column still gives an error of order one.
+    d = np.sqrt(np.sum((g - ref["g"]) ** 2, axis=-1))
+    norm = np.sqrt(np.sum(ref["g"] ** 2, axis=-1))
+    nw = float((d / np.maximum(norm, 0.01 * np.median(norm))).max())
+    _say("  g normwise %.3g (floor: 1%% of the median spectrum norm)" % nw)
     assert nw <= FIR_RTOL[prec]
 
 

@@ -32,10 +32,25 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+# Every stream test runs on both kernel paths (fe_stream_set_schedule): the
+# split path (FIR kernel, filtered samples in device memory, FFT/post kernel)
+# and the fused kernel (FP32, n <= 4096, T <= 16; other shapes run split
+# either way).
+PATH = {"now": "split"}
+
+
+@pytest.fixture(autouse=True, params=["split", "fused"])
+def kernel_path(request):
+    PATH["now"] = request.param
+    _say("[path %s]" % request.param)
+    yield request.param
+    PATH["now"] = "split"
+
+
 def make_stream(w, max_samples, max_delay=128):
     s = w.shape
     return fe.Stream(s.n, s.taps, s.antennas, w.weights, max_samples,
-                     spectra_per_heap=s.spectra_per_heap, max_delay=max_delay)
+                     spectra_per_heap=s.spectra_per_heap, max_delay=max_delay, path=PATH["now"])
 
 
 def gpu_run(w, chunk, mode="int8", max_delay=128, stream=None):
@@ -136,7 +151,7 @@ def test_hot_path_unpack_every_code_and_phase(prec):
     w.weights = np.ones_like(w.weights)
     F = np.arange(M * calls)
     w.delays[:] = ((F * 7 + 13 * np.arange(4).reshape(2, 2, 1)) % 121).astype(np.float64)
-    st = fe.Stream(n, 1, 2, w.weights, 2 * n * M, spectra_per_heap=S, precision=prec)
+    st = fe.Stream(n, 1, 2, w.weights, 2 * n * M, spectra_per_heap=S, precision=prec, path=PATH["now"])
     g, status = gpu_run(w, 2 * n * M, mode="fir", stream=st)
     st.close()
     assert status == fe.FE_OK
@@ -336,8 +351,13 @@ def test_host_validation_with_live_stream():
     with pytest.raises(fe.FEngineError) as e:
         st.channelize(dev(raw), w.total // 2 + 2 * n, dev(d), dev(p), dev(w.gains), o)
     assert e.value.status == fe.FE_EINVAL
+    # more samples than the stream was created for: the library refuses the
+    # call (the buffers are large enough, so the binding passes it on)
+    raw2 = np.concatenate([raw, raw], axis=-1)
+    d2, p2 = np.concatenate([d, d], axis=-1), np.concatenate([p, p], axis=-1)
+    o2 = torch.empty((1, 2 * M // S, n, S, 2, 2), dtype=torch.int8, device="cuda")
     with pytest.raises(fe.FEngineError) as e:
-        st.channelize(dev(raw), 2 * w.total, dev(d), dev(p), dev(w.gains), o)
+        st.channelize(dev(raw2), 2 * w.total, dev(d2), dev(p2), dev(w.gains), o2)
     assert e.value.status == fe.FE_ESIZE
     # an empty call is not a whole number of heaps either
     with pytest.raises(fe.FEngineError) as e:
