@@ -152,6 +152,32 @@ fe_status fe_channelize_prequant(fe_stream *s, const uint8_t *raw, int64_t n_sam
 fe_status fe_channelize_fir(fe_stream *s, const uint8_t *raw, int64_t n_samples,
                             const double *delays, float *g_out);
 
+/* Bytes of the static device scratch of fe_channelize_noalloc, on every GPU
+ * the library runs on. */
+#define FE_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * call, output and stream-state update as fe_channelize, with the call's
+ * intermediate buffers (filtered samples, int8 spectra before the corner
+ * turn, the two-level FFT's reordered gains, the history assembly of calls
+ * shorter than the history) in a static device array of the library,
+ * FE_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, instead of
+ * the stream's workspace.  Allocates nothing and does not synchronize.  A
+ * call needs 4 bytes per real sample for the filtered samples (none on the
+ * fused path), 1 byte per real sample for the int8 spectra, 16n bytes per
+ * antenna when n > 8192 and 2.5 H bytes per antenna when n_samples < H,
+ * each rounded up to 256 bytes; a call needing more than
+ * FE_NOALLOC_SCRATCH_BYTES returns FE_ESIZE before anything is enqueued.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (on different HIP streams, or from several host threads) race and
+ * corrupt each other's results; calls enqueued on one HIP stream are
+ * ordered and safe.  No part of the scratch is read before the call writes
+ * it, so nothing needs clearing between calls. */
+fe_status fe_channelize_noalloc(fe_stream *s, const uint8_t *raw, int64_t n_samples,
+                                const double *delays, const double *phases, const float *gains,
+                                int8_t *out);
+
 /* Synchronize the stream's HIP stream and return its sticky status:
  * FE_OK, FE_EDELAY (cleared only by fe_stream_reset), or FE_EHIP. */
 fe_status fe_stream_status(fe_stream *s);

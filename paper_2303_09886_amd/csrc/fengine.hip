@@ -32,6 +32,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1999,6 +2000,18 @@ __global__ void unpack_kernel(const uint8_t *__restrict__ raw, int64_t first, in
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Static device scratch of fe_channelize_noalloc: the intermediate buffers of
+// a call (filtered samples, int8 spectra before the corner turn, reordered
+// gains, history assembly), FE_NOALLOC_SCRATCH_BYTES on every GPU the library
+// runs on, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, not the device array: its device address comes from
+// hipGetSymbolAddress, once per device (scratch_address), and only that
+// address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) uint8_t scratch[FE_NOALLOC_SCRATCH_BYTES];
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -2183,6 +2196,36 @@ std::vector<float2> tw16_for(int n)
 
 fe_status hip_status(hipError_t e) { return e == hipSuccess ? FE_OK : FE_EHIP; }
 
+// Device address of the static scratch on `device`, which must be the
+// current device: looked up once per device (at the first stream creation
+// on it), NULL if the lookup failed.
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+uint8_t *g_scratch_ptr[kMaxDevices];
+
+uint8_t *scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return nullptr;
+    std::call_once(g_scratch_once[device], [device]() {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[device] = e == hipSuccess ? static_cast<uint8_t *>(p) : nullptr;
+        if (e != hipSuccess)
+            (void)hipGetLastError();
+    });
+    return g_scratch_ptr[device];
+}
+
+// Per-call intermediate buffers of a call: the stream's own workspace, or
+// the library's static scratch (fe_channelize_noalloc).
+struct Work {
+    float *g;               // filtered samples g (float32; FP16 streams store FP16)
+    uint32_t *spec8;        // int8 spectra before the corner turn
+    float2 *gpl;            // n > 8192: the call's gains in residue-plane order
+    uint8_t *hist_tmp;      // history assembly for calls shorter than H
+};
+
 template <int T>
 void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g,
                   int mb, int me)
@@ -2260,100 +2303,100 @@ void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double 
 }
 
 template <int N>
-void launch_post_N(const fe_stream *s, int M, const double *delays, const double *phases,
+void launch_post_N(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
                    const float *gains, float *y_out, int mb, int me)
 {
     const unsigned blocks = unsigned(s->A * (me - mb) * 2);
     if (y_out)
         hipLaunchKernelGGL((fft_post_kernel<N, OUT_PREQUANT>), dim3(blocks), dim3(N / 16), 0, s->stream,
-                           s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
-                           s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status,
+                           wk.g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status,
                            M, s->D, mb, me);
     else
         hipLaunchKernelGGL((fft_post_kernel<N, OUT_INT8>), dim3(blocks), dim3(N / 16), 0, s->stream,
-                           s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
-                           s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status,
+                           wk.g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status,
                            M, s->D, mb, me);
 }
 
 template <int N, int PREC>
-void launch_post_mfma_N(const fe_stream *s, int M, const double *delays, const double *phases,
+void launch_post_mfma_N(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
                         const float *gains, float *y_out, int mb, int me)
 {
     const unsigned blocks = unsigned(s->A * (me - mb) * 2);
     const u32x4 *dfta = reinterpret_cast<const u32x4 *>(s->d_dfta);
     if (y_out)
         hipLaunchKernelGGL((fft_mfma_kernel<N, PREC, OUT_PREQUANT>), dim3(blocks), dim3(MPlan<N>::NT), 0,
-                           s->stream, s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains),
-                           s->d_tw16, s->d_untangle, dfta, s->d_spec8, reinterpret_cast<float2 *>(y_out),
+                           s->stream, wk.g, delays, phases, reinterpret_cast<const float2 *>(gains),
+                           s->d_tw16, s->d_untangle, dfta, wk.spec8, reinterpret_cast<float2 *>(y_out),
                            s->d_status, M, s->D, mb, me);
     else
         hipLaunchKernelGGL((fft_mfma_kernel<N, PREC, OUT_INT8>), dim3(blocks), dim3(MPlan<N>::NT), 0,
-                           s->stream, s->d_g, delays, phases, reinterpret_cast<const float2 *>(gains),
-                           s->d_tw16, s->d_untangle, dfta, s->d_spec8, reinterpret_cast<float2 *>(y_out),
+                           s->stream, wk.g, delays, phases, reinterpret_cast<const float2 *>(gains),
+                           s->d_tw16, s->d_untangle, dfta, wk.spec8, reinterpret_cast<float2 *>(y_out),
                            s->d_status, M, s->D, mb, me);
 }
 
 template <int PREC>
-void launch_post_mfma(const fe_stream *s, int M, const double *delays, const double *phases,
+void launch_post_mfma(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
                       const float *gains, float *y_out, int mb, int me)
 {
     switch (s->n) {
-    case 256: launch_post_mfma_N<256, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 512: launch_post_mfma_N<512, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 1024: launch_post_mfma_N<1024, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 2048: launch_post_mfma_N<2048, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 4096: launch_post_mfma_N<4096, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 8192: launch_post_mfma_N<8192, PREC>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 256: launch_post_mfma_N<256, PREC>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 512: launch_post_mfma_N<512, PREC>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 1024: launch_post_mfma_N<1024, PREC>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 2048: launch_post_mfma_N<2048, PREC>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 4096: launch_post_mfma_N<4096, PREC>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 8192: launch_post_mfma_N<8192, PREC>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
     }
 }
 
 template <int NL>
-void launch_post_large(const fe_stream *s, int M, const double *delays, const double *phases,
+void launch_post_large(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
                        const float *gains, float *y_out, int mb, int me)
 {
     const int64_t fthreads = int64_t(s->A) * 2 * (me - mb) * (NL / 16);
     hipLaunchKernelGGL(fft_front_kernel, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0, s->stream,
-                       s->d_g, s->d_twf, reinterpret_cast<const float2 *>(gains), s->d_gpl, NL, M, mb, me, s->A);
+                       wk.g, s->d_twf, reinterpret_cast<const float2 *>(gains), wk.gpl, NL, M, mb, me, s->A);
     const unsigned blocks = unsigned(s->A * (me - mb) * 2);
     if (y_out)
         hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_PREQUANT>), dim3(blocks), dim3(NL / 128), 0,
-                           s->stream, s->d_g, delays, phases, s->d_gpl, s->d_tw,
-                           s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
+                           s->stream, wk.g, delays, phases, wk.gpl, s->d_tw,
+                           s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
                            mb, me);
     else
         hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_INT8>), dim3(blocks), dim3(NL / 128), 0,
-                           s->stream, s->d_g, delays, phases, s->d_gpl, s->d_tw,
-                           s->d_untangle, s->d_spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
+                           s->stream, wk.g, delays, phases, wk.gpl, s->d_tw,
+                           s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
                            mb, me);
 }
 
-void launch_post(const fe_stream *s, int M, const double *delays, const double *phases,
+void launch_post(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
                  const float *gains, float *y_out, int mb, int me)
 {
     if (s->n == 16384) {
-        launch_post_large<16384>(s, M, delays, phases, gains, y_out, mb, me);
+        launch_post_large<16384>(s, wk, M, delays, phases, gains, y_out, mb, me);
         return;
     }
     if (s->n == 32768) {
-        launch_post_large<32768>(s, M, delays, phases, gains, y_out, mb, me);
+        launch_post_large<32768>(s, wk, M, delays, phases, gains, y_out, mb, me);
         return;
     }
     if (s->prec == FE_PREC_FP16) {
-        launch_post_mfma<FE_PREC_FP16>(s, M, delays, phases, gains, y_out, mb, me);
+        launch_post_mfma<FE_PREC_FP16>(s, wk, M, delays, phases, gains, y_out, mb, me);
         return;
     }
     if (s->prec == FE_PREC_BF16) {
-        launch_post_mfma<FE_PREC_BF16>(s, M, delays, phases, gains, y_out, mb, me);
+        launch_post_mfma<FE_PREC_BF16>(s, wk, M, delays, phases, gains, y_out, mb, me);
         return;
     }
     switch (s->n) {
-    case 256: launch_post_N<256>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 512: launch_post_N<512>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 1024: launch_post_N<1024>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 2048: launch_post_N<2048>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 4096: launch_post_N<4096>(s, M, delays, phases, gains, y_out, mb, me); break;
-    case 8192: launch_post_N<8192>(s, M, delays, phases, gains, y_out, mb, me); break;
+    case 256: launch_post_N<256>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 512: launch_post_N<512>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 1024: launch_post_N<1024>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 2048: launch_post_N<2048>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 4096: launch_post_N<4096>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
+    case 8192: launch_post_N<8192>(s, wk, M, delays, phases, gains, y_out, mb, me); break;
     }
 }
 
@@ -2392,7 +2435,7 @@ unsigned fused_blocks(const fe_stream *s, int n, int64_t units)
 }
 
 template <int N, int T>
-void launch_fused_NT(const fe_stream *s, const uint8_t *raw, int64_t Ns, const double *delays,
+void launch_fused_NT(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t Ns, const double *delays,
                      const double *phases, const float *gains, float *y_out, float *g_out, int mb, int me)
 {
     const int M = int(Ns / (2 * N));
@@ -2406,47 +2449,47 @@ void launch_fused_NT(const fe_stream *s, const uint8_t *raw, int64_t Ns, const d
     if (g_out)
         hipLaunchKernelGGL((pfb_fused_kernel<N, T, OUT_G>), dim3(blocks), dim3(N / 4), 0, s->stream,
                            raw, rstride, s->d_hist, hstride, s->H, s->d_taps, delays, phases, gn, s->d_tw,
-                           s->d_untangle, s->d_spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
+                           s->d_untangle, wk.spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
     else if (y_out)
         hipLaunchKernelGGL((pfb_fused_kernel<N, T, OUT_PREQUANT>), dim3(blocks), dim3(N / 4), 0, s->stream,
                            raw, rstride, s->d_hist, hstride, s->H, s->d_taps, delays, phases, gn, s->d_tw,
-                           s->d_untangle, s->d_spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
+                           s->d_untangle, wk.spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
     else
         hipLaunchKernelGGL((pfb_fused_kernel<N, T, OUT_INT8>), dim3(blocks), dim3(N / 4), 0, s->stream,
                            raw, rstride, s->d_hist, hstride, s->H, s->d_taps, delays, phases, gn, s->d_tw,
-                           s->d_untangle, s->d_spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
+                           s->d_untangle, wk.spec8, y2, g2, s->d_status, M, s->D, streams, mb, me);
 }
 
 template <int N>
-void launch_fused_N(const fe_stream *s, const uint8_t *raw, int64_t Ns, const double *delays,
+void launch_fused_N(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t Ns, const double *delays,
                     const double *phases, const float *gains, float *y_out, float *g_out, int mb, int me)
 {
     switch (s->Tk) {
-    case 4: launch_fused_NT<N, 4>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
-    case 8: launch_fused_NT<N, 8>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
-    case 16: launch_fused_NT<N, 16>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 4: launch_fused_NT<N, 4>(s, wk, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 8: launch_fused_NT<N, 8>(s, wk, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 16: launch_fused_NT<N, 16>(s, wk, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
     }
 }
 
-void launch_fused(const fe_stream *s, const uint8_t *raw, int64_t Ns, const double *delays,
+void launch_fused(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t Ns, const double *delays,
                   const double *phases, const float *gains, float *y_out, float *g_out, int mb, int me)
 {
     switch (s->n) {
-    case 256: launch_fused_N<256>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
-    case 512: launch_fused_N<512>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
-    case 1024: launch_fused_N<1024>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
-    case 2048: launch_fused_N<2048>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
-    case 4096: launch_fused_N<4096>(s, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 256: launch_fused_N<256>(s, wk, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 512: launch_fused_N<512>(s, wk, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 1024: launch_fused_N<1024>(s, wk, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 2048: launch_fused_N<2048>(s, wk, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
+    case 4096: launch_fused_N<4096>(s, wk, raw, Ns, delays, phases, gains, y_out, g_out, mb, me); break;
     }
 }
 
-void launch_corner_turn(const fe_stream *s, int M, int8_t *out)
+void launch_corner_turn(const fe_stream *s, const Work &wk, int M, int8_t *out)
 {
     const int ftiles = (M + CT - 1) / CT, ktiles = s->n / CT;
     // the two-level FFT (n > 8192, FP32) leaves its spectra as 16 residue planes
     const int ns = s->n > 8192 ? s->n / 16 : 0;
     hipLaunchKernelGGL(corner_turn_kernel, dim3(unsigned(s->A * ftiles * ktiles)), dim3(256), 0,
-                       s->stream, s->d_spec8, out, M, s->n, s->S, ftiles, ktiles, ns);
+                       s->stream, wk.spec8, out, M, s->n, s->S, ftiles, ktiles, ns);
 }
 
 unsigned grid_for(int64_t work, int threads)
@@ -2459,7 +2502,7 @@ unsigned grid_for(int64_t work, int threads)
     return unsigned(b);
 }
 
-void launch_history_update(const fe_stream *s, const uint8_t *raw, int64_t N)
+void launch_history_update(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N)
 {
     const int streams = 2 * s->A;
     const int64_t hb = int64_t(s->H) * 5 / 4;     // history bytes per stream
@@ -2471,11 +2514,11 @@ void launch_history_update(const fe_stream *s, const uint8_t *raw, int64_t N)
         // new history = old[N:] ++ chunk, assembled in the spare buffer first
         const int64_t keep = hb - nb;
         hipLaunchKernelGGL(copy_rows_kernel, dim3(grid_for(keep * streams, 256)), dim3(256), 0, s->stream,
-                           s->d_hist_tmp, hb, int64_t(0), s->d_hist, hb, nb, keep, streams);
+                           wk.hist_tmp, hb, int64_t(0), s->d_hist, hb, nb, keep, streams);
         hipLaunchKernelGGL(copy_rows_kernel, dim3(grid_for(nb * streams, 256)), dim3(256), 0, s->stream,
-                           s->d_hist_tmp, hb, keep, raw, nb, int64_t(0), nb, streams);
+                           wk.hist_tmp, hb, keep, raw, nb, int64_t(0), nb, streams);
         hipLaunchKernelGGL(copy_rows_kernel, dim3(grid_for(hb * streams, 256)), dim3(256), 0, s->stream,
-                           s->d_hist, hb, int64_t(0), s->d_hist_tmp, hb, int64_t(0), hb, streams);
+                           s->d_hist, hb, int64_t(0), wk.hist_tmp, hb, int64_t(0), hb, streams);
     }
 }
 
@@ -2491,15 +2534,42 @@ fe_status check_call(const fe_stream *s, const uint8_t *raw, int64_t N, const do
     return FE_OK;
 }
 
+// Bytes of static scratch a call of N samples needs (fe_channelize_noalloc):
+// the regions of Work, each rounded up to 256 bytes.
+int64_t scratch_need(const fe_stream *s, int64_t N, int64_t *off_spec8, int64_t *off_gpl, int64_t *off_hist)
+{
+    auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+    const int64_t streams = 2 * int64_t(s->A);
+    const int64_t g = fused_path(s) ? 0 : up(streams * N * 4);
+    const int64_t spec8 = up(streams * N);
+    const int64_t gpl = s->n > 8192 ? up(streams * s->n * 8) : 0;
+    const int64_t hist = N < s->H ? up(streams * (int64_t(s->H) * 5 / 4)) : 0;
+    *off_spec8 = g;
+    *off_gpl = g + spec8;
+    *off_hist = g + spec8 + gpl;
+    return g + spec8 + gpl + hist;
+}
+
 fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const double *delays,
                           const double *phases, const float *gains, int8_t *out, float *y_out,
-                          float *g_out)
+                          float *g_out, uint8_t *scratch_base = nullptr)
 {
     fe_status st = check_call(s, raw, N, delays);
     if (st != FE_OK)
         return st;
     if (!g_out && (!phases || !gains || (!out && !y_out)))
         return FE_EINVAL;
+    Work wk = {s->d_g, s->d_spec8, s->d_gpl, s->d_hist_tmp};
+    if (scratch_base) {
+        // the static scratch in place of the stream's workspace
+        int64_t o_spec8, o_gpl, o_hist;
+        if (scratch_need(s, N, &o_spec8, &o_gpl, &o_hist) > int64_t(FE_NOALLOC_SCRATCH_BYTES))
+            return FE_ESIZE;
+        wk.g = reinterpret_cast<float *>(scratch_base);
+        wk.spec8 = reinterpret_cast<uint32_t *>(scratch_base + o_spec8);
+        wk.gpl = reinterpret_cast<float2 *>(scratch_base + o_gpl);
+        wk.hist_tmp = scratch_base + o_hist;
+    }
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess)
         return FE_EHIP;
@@ -2517,17 +2587,17 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
     mark(0);
     const bool fused = fused_path(s);
     if (fused)
-        launch_fused(s, raw, N, delays, phases, gains, y_out, g_out, 0, M);
+        launch_fused(s, wk, raw, N, delays, phases, gains, y_out, g_out, 0, M);
     else
-        launch_fir(s, raw, N, delays, g_out ? g_out : s->d_g, 0, M, g_out != nullptr);
+        launch_fir(s, raw, N, delays, g_out ? g_out : wk.g, 0, M, g_out != nullptr);
     mark(1);
-    launch_history_update(s, raw, N);
+    launch_history_update(s, wk, raw, N);
     mark(2);
     if (!g_out && !fused)
-        launch_post(s, M, delays, phases, gains, y_out, 0, M);
+        launch_post(s, wk, M, delays, phases, gains, y_out, 0, M);
     mark(3);
     if (!g_out && !y_out)
-        launch_corner_turn(s, M, out);
+        launch_corner_turn(s, wk, M, out);
     mark(4);
     st = hip_status(hipGetLastError());
     if (cur != s->device)
@@ -2624,6 +2694,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
         return FE_EHIP;
     }
     s->cus = std::max(s->cus, 8);
+    (void)scratch_address(s->device);       // set-up of fe_channelize_noalloc's scratch on this device
 
     const int streams = 2 * s->A;
     const int64_t n2 = 2 * int64_t(n);
@@ -2729,6 +2800,17 @@ fe_status fe_channelize(fe_stream *s, const uint8_t *raw, int64_t n_samples, con
     if (!out)
         return FE_EINVAL;
     return channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr);
+}
+
+fe_status fe_channelize_noalloc(fe_stream *s, const uint8_t *raw, int64_t n_samples, const double *delays,
+                                const double *phases, const float *gains, int8_t *out)
+{
+    if (!s || !out)
+        return FE_EINVAL;
+    uint8_t *base = scratch_address(s->device);
+    if (!base)
+        return FE_EHIP;
+    return channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr, base);
 }
 
 fe_status fe_channelize_prequant(fe_stream *s, const uint8_t *raw, int64_t n_samples,

@@ -15,6 +15,7 @@ from typing import Optional
 from . import build as _build
 
 FE_OK, FE_EINVAL, FE_ENOMEM, FE_EHIP, FE_EDELAY, FE_ESIZE = 0, -1, -2, -3, -4, -5
+FE_NOALLOC_SCRATCH_BYTES = 64 << 20         # include/fengine.h
 FE_PREC_FP32, FE_PREC_FP16, FE_PREC_BF16 = 0, 1, 2
 PRECISIONS = {"fp32": FE_PREC_FP32, "fp16": FE_PREC_FP16, "bf16": FE_PREC_BF16}
 FE_PATH_AUTO, FE_PATH_SPLIT, FE_PATH_FUSED = 0, 1, 2
@@ -63,7 +64,7 @@ def load_library(path: Optional[str] = None):
     L.fe_stream_set_hip_stream.restype = _st
     L.fe_stream_reset.argtypes = [_vp]
     L.fe_stream_reset.restype = _st
-    for name in ("fe_channelize", "fe_channelize_prequant"):
+    for name in ("fe_channelize", "fe_channelize_prequant", "fe_channelize_noalloc"):
         f = getattr(L, name)
         f.argtypes = [_vp, _vp, _i64, _vp, _vp, _vp, _vp]
         f.restype = _st
@@ -261,6 +262,14 @@ class Stream:
         a = self._args(raw, n_samples, delays, phases, gains) + [_ptr(out, torch.int8, "out")]
         check_sizes(self.A, self.n, n_samples, out=out)
         _check(load_library().fe_channelize(*a), "fe_channelize")
+
+    def channelize_noalloc(self, raw, n_samples: int, delays, phases, gains, out):
+        """Enqueue fe_channelize_noalloc (the call's intermediate buffers in the
+        library's static device scratch; see the header for its limit)."""
+        import torch
+        a = self._args(raw, n_samples, delays, phases, gains) + [_ptr(out, torch.int8, "out")]
+        check_sizes(self.A, self.n, n_samples, out=out)
+        _check(load_library().fe_channelize_noalloc(*a), "fe_channelize_noalloc")
 
     def channelize_prequant(self, raw, n_samples: int, delays, phases, gains, y_out):
         """Enqueue fe_channelize_prequant; ``y_out`` float32 [A][2][M][n][2]."""
