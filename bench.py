@@ -349,8 +349,8 @@ def main():
     ap.add_argument("--cpu-spectra", type=int, default=None,
                     help="spectra per antenna for the CPU baseline (default: all)")
     ap.add_argument("--variants", default="fp16,bf16,fused",
-                    help="variants timed beside the FP32 path: fp16, bf16 (matrix cores), fused "
-                         "(the FP32 stream on the fused kernel); comma list, empty for none")
+                    help="variants timed beside the FP32 path: fp16, bf16 (matrix cores), split, fused "
+                         "(the FP32 stream on those kernel paths); comma list, empty for none")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-stream batch measurement")
     ap.add_argument("--no-service", action="store_true", help="skip the streaming-service measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -393,10 +393,10 @@ def main():
     res = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup)
     variants = {}
     for prec in args.variants.split(",") if args.variants else []:
-        if prec == "fused":
-            # the same FP32 stream on the fused kernel (fe_stream_set_schedule)
-            variants["fp32_fused"] = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup,
-                                             path="fused")
+        if prec in ("fused", "split"):
+            # the same FP32 stream on another kernel path (fe_stream_set_schedule)
+            variants["fp32_" + prec] = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup,
+                                               path=prec)
             continue
         r = measure(fe, shape, w, sets, dev_arrays, prec, args.steps, args.warmup)
         variants[prec + "_mfma"] = r

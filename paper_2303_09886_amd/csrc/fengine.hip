@@ -183,16 +183,16 @@ __device__ __forceinline__ float field10(uint32_t u, uint32_t lo_shift)
     return float(x);
 }
 
+// The body of kernel 1 for logical block lb (tile: stream, run, column
+// block); s_c is an LDS table of FIR_SEG ints.
 template <int T>
-__global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
+__device__ __forceinline__ void fir_block(
+    int lb, int *__restrict__ s_c,
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
     float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me)
 {
-    __shared__ int s_c[FIR_SEG];            // coarse delay of each spectrum of the segment, -1 if invalid
-
-    const int lb = xcd_logical(blockIdx.x, gridDim.x);
     const int cb = lb % colblocks;
     const int rest = lb / colblocks;
     const int run = rest % runs;
@@ -370,6 +370,18 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
         }
     }
     flush();
+}
+
+template <int T>
+__global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
+    const uint8_t *__restrict__ raw, int64_t raw_stride,
+    const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
+    const float *__restrict__ taps, const double *__restrict__ delays,
+    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me)
+{
+    __shared__ int s_c[FIR_SEG];            // coarse delay of each spectrum of the segment, -1 if invalid
+    fir_block<T>(xcd_logical(blockIdx.x, gridDim.x), s_c, raw, raw_stride, hist, hist_stride, H, taps,
+                 delays, g, n2, M, D, R, colblocks, runs, mb, me);
 }
 
 // ---------------------------------------------------------------------------
@@ -617,7 +629,8 @@ template <int N, int NT, int MODE>
 __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, const float2 *ph_hi,
                                               const float2 *ph_lo, const float2 *__restrict__ untangle,
                                               const float2 *__restrict__ gn, bool ok, int64_t sp, int tid,
-                                              uint32_t *__restrict__ spec8, float2 *__restrict__ y_out)
+                                              uint32_t *__restrict__ spec8, float2 *__restrict__ y_out,
+                                              bool store = true)
 {
     // channel k = k0 + S i with k0 = 2 tid + e: the padded LDS offsets of k
     // and n - k, the coarse phase index and the table offsets all step by
@@ -665,7 +678,8 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
             const float2 rot = cmul(ph_hi[k >> 6], l);                 // includes 1/2
             Y[e] = ok ? cmul(gk, cmul(rot, X2)) : make_float2(0.f, 0.f);
         }
-        if (MODE == OUT_PREQUANT) {
+        if (!store) {
+        } else if (MODE == OUT_PREQUANT) {
             reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
         } else {
             spec8[sp * (N / 2) + j] = quant4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
@@ -673,8 +687,15 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
     }
 }
 
+// The body of kernel 2 for one work item ((a (me - mb) + F - mb) * 2 + p:
+// both pols of a spectrum adjacent) by threads tid < n/16, with LDS buf
+// (lds_len<N>), ph_hi (max(N/64, 1)) and ph_lo (64).  An item that is not
+// `valid` runs the same arithmetic (and barriers) on item 0 and stores
+// nothing.
 template <int N, int MODE>
-__global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kernel(
+__device__ __forceinline__ void fft_post_block(
+    int item, bool valid, int tid, float2 *__restrict__ buf, float2 *__restrict__ ph_hi,
+    float2 *__restrict__ ph_lo,
     const float *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw_all, const float2 *__restrict__ untangle,
@@ -683,19 +704,12 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
 {
     static_assert(Plan<N>::R[0] == 16, "plans start with a radix-16 pass");
     constexpr int NT = N / 16;             // threads, 16 points each
-    constexpr int NH = N / 64;             // coarse phase-table entries (k >> 6)
-    constexpr int NP = lds_len<N>();
-    __shared__ float2 buf[NP];
-    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
-    __shared__ float2 ph_lo[64];
-
-    // work item ((a (me - mb) + F - mb) * 2 + p): both pols of a spectrum adjacent
-    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    if (!valid)
+        item = 0;
     const int p = item & 1;
     const int af = item >> 1;
     const int a = af / (me - mb);
     const int F = mb + af % (me - mb);
-    const int tid = threadIdx.x;
     const int64_t sp = (int64_t(a) * 2 + p) * M + F;          // stream spectrum
 
     // z[m] = g[2m] + i g[2m+1]
@@ -708,7 +722,7 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
     int c;
     double tau;
     const bool ok = split_delay(delays[sp], D, c, tau);
-    if (!ok && tid == 0)
+    if (valid && !ok && tid == 0)
         atomicOr(status, 1);
     phase_tables<N, NT>(ph_hi, ph_lo, phases[sp], tau, 0.5f, tid);
 
@@ -721,7 +735,23 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
     fft_rest<N, 1>(buf, tid, tw_all);
 
     post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
-                               tid, spec8, y_out);
+                               tid, spec8, y_out, valid);
+}
+
+template <int N, int MODE>
+__global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kernel(
+    const float *__restrict__ g, const double *__restrict__ delays,
+    const double *__restrict__ phases, const float2 *__restrict__ gains,
+    const float2 *__restrict__ tw_all, const float2 *__restrict__ untangle,
+    uint32_t *__restrict__ spec8, float2 *__restrict__ y_out, int *__restrict__ status,
+    int M, int D, int mb, int me)
+{
+    constexpr int NH = N / 64;             // coarse phase-table entries (k >> 6)
+    __shared__ float2 buf[lds_len<N>()];
+    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[64];
+    fft_post_block<N, MODE>(xcd_logical(blockIdx.x, gridDim.x), true, threadIdx.x, buf, ph_hi, ph_lo, g,
+                            delays, phases, gains, tw_all, untangle, spec8, y_out, status, M, D, mb, me);
 }
 
 // ---------------------------------------------------------------------------
@@ -1916,16 +1946,17 @@ constexpr int CT = 64;                     // tile edge (spectra and channels)
 // spec8 holds each spectrum either in channel order or, for the two-level
 // FFT (ns = n/16), as 16 planes of ns channels: position j = d ns + k' is
 // channel d + 16 k'.  A tile never straddles planes (ns is a multiple of 64).
-__global__ __launch_bounds__(256) void corner_turn_kernel(
+// The body for block b of a launch over spectrum tiles ft0 .. ft0 + ftiles - 1
+// (all antennas); t16 is an LDS tile.
+__device__ __forceinline__ void corner_turn_block(
+    int b, int ft0, uint16_t (*__restrict__ t16)[2 * CT + 2],
     const uint32_t *__restrict__ spec8, int8_t *__restrict__ out, int M, int n, int S,
     int ftiles, int ktiles, int ns)
 {
     // t16[f][2k + p] = (re, im) of channel k0+k, pol p, spectrum F0+f
-    __shared__ uint16_t t16[CT][2 * CT + 2];
-    const int b = blockIdx.x;
     const int kt = b % ktiles;
     const int rest = b / ktiles;
-    const int ft = rest % ftiles;
+    const int ft = ft0 + rest % ftiles;
     const int a = rest / ftiles;
     const int F0 = ft * CT, k0 = kt * CT;
     const int tid = threadIdx.x;
@@ -1956,6 +1987,14 @@ __global__ __launch_bounds__(256) void corner_turn_kernel(
             __builtin_nontemporal_store(d, reinterpret_cast<uint32_t *>(out) + idx);
         }
     }
+}
+
+__global__ __launch_bounds__(256) void corner_turn_kernel(
+    const uint32_t *__restrict__ spec8, int8_t *__restrict__ out, int M, int n, int S,
+    int ftiles, int ktiles, int ns)
+{
+    __shared__ uint16_t t16[CT][2 * CT + 2];
+    corner_turn_block(blockIdx.x, 0, t16, spec8, out, M, n, S, ftiles, ktiles, ns);
 }
 
 // ---------------------------------------------------------------------------
@@ -2417,6 +2456,7 @@ bool fused_path(const fe_stream *s)
         return false;
     return s->path == FE_PATH_FUSED || (s->Tk <= 8 && s->n <= 2048);
 }
+
 
 // Workgroups of the fused kernel: a multiple of 8 (one share per XCD), at
 // most what the GPU holds at once (s->fir_batches, when tuned, sets the
