@@ -143,9 +143,11 @@ def stored_traffic(kernel: str):
 
 
 def measure_batch(fe, steps: int, warmup: int, tune: bool = True):
-    """The 16-stream uneven batch: every step runs one call of each stream;
-    timed as one graph launch per step, and as the same calls issued stream
-    after stream on one HIP stream (no overlap) for comparison."""
+    """The 16-stream uneven batch: every step runs one call of each stream.
+    Timed as one graph launch per step with the launches grouped across the
+    members (job-list kernels), as one graph launch per step with every
+    member's kernels on a fork stream of its own, and as the same calls
+    issued stream after stream on one HIP stream (no overlap)."""
     import torch
     shapes = synth.BATCH16
     streams, bufs = [], []
@@ -162,40 +164,53 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True):
         streams.append(st)
         bufs.append(b)
     torch.cuda.synchronize()
-    choices = [st.autotune(*b, iters=2) for st, b in zip(streams, bufs)] if tune else None
+    if tune:
+        for st, b in zip(streams, bufs):
+            st.autotune(*b, iters=2)
+    # the tuned schedule of every member: kernel path and FIR run length /
+    # workgroups per CU (two knobs per stream)
+    choices = [list(st.schedule()) for st in streams]
     total = sum(2 * sh.samples for sh in shapes)
-    # sequential reference: each stream's call after the previous one
-    for _ in range(warmup):
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    def sequential():
         for st, b in zip(streams, bufs):
             st.channelize(*b)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        for st, b in zip(streams, bufs):
-            st.channelize(*b)
-    torch.cuda.synchronize()
-    seq_ms = (time.perf_counter() - t0) * 1e3 / steps
-    batch = fe.Batch(streams)
-    batch.capture(bufs)
-    for _ in range(warmup):
-        batch.launch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        batch.launch()
-    torch.cuda.synchronize()
-    g_ms = (time.perf_counter() - t0) * 1e3 / steps
-    batch.close()
+
+    seq_ms = timed(sequential)
+    res = {}
+    for grouped in (True, False):
+        batch = fe.Batch(streams)
+        batch.set_grouped(grouped)
+        batch.capture(bufs)
+        res[grouped] = timed(batch.launch)
+        batch.close()
     for st in streams:
         if st.status() != fe.FE_OK:
             log("warning: batch member status %d" % st.status())
         st.close()
+    g_ms = res[True]
     return {"value": round(total / (g_ms * 1e-3) / 1e9, 2), "unit": "Gsample/s", "ms_per_step": round(g_ms, 4),
+            "per_member_launches_ms_per_step": round(res[False], 4),
+            "per_member_launches_value": round(total / (res[False] * 1e-3) / 1e9, 2),
             "sequential_ms_per_step": round(seq_ms, 4),
             "sequential_value": round(total / (seq_ms * 1e-3) / 1e9, 2),
-            "streams": len(shapes), "samples_per_step": total, "fir_run_choices": choices,
+            "streams": len(shapes), "samples_per_step": total,
+            "tuned_schedule": {"knobs": ["path (split|fused)", "fir_batches (FIR run length in batches of "
+                                         "spectra, or fused workgroups per CU; 0 = per-launch default)"],
+                               "per_stream": choices},
             "config": "16 single-antenna streams, channels 1024/4096/8192/32768, taps 8/16/24, "
-                      "2^22..2^24 samples/pol each, heaps of 64 spectra, one HIP-graph launch per step"}
+                      "2^22..2^24 samples/pol each, heaps of 64 spectra, one HIP-graph launch per step "
+                      "(FP32 split-path members through job-list kernels grouped by tap count and channel count)"}
 
 
 def measure_service(chunks: int = 24, seed: int = 3):

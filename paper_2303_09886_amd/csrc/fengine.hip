@@ -185,13 +185,19 @@ __device__ __forceinline__ float field10(uint32_t u, uint32_t lo_shift)
 
 // The body of kernel 1 for logical block lb (tile: stream, run, column
 // block); s_c is an LDS table of FIR_SEG ints.
+// Rows come from `raw` (mrows rows of 2n samples per stream, row 0 at the
+// start of raw); spectrum m of that row numbering is spectrum m - moff of the
+// call (its delay and its filtered samples).  The call's own chunk has
+// moff = 0, mrows = M; a staged seam (the history's tail and the chunk's first
+// rows, one buffer per stream) has moff = its rows before the chunk.
 template <int T>
 __device__ __forceinline__ void fir_block(
     int lb, int *__restrict__ s_c,
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
-    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me)
+    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
+    int moff, int mrows)
 {
     const int cb = lb % colblocks;
     const int rest = lb / colblocks;
@@ -247,7 +253,7 @@ __device__ __forceinline__ void fir_block(
         for (int r = 0; r < T; ++r) {
             asm volatile("" : "+s"(rp));
             N[r] = load_u16(rp, voff);
-            if (g0 + r + 1 < M)
+            if (g0 + r + 1 < mrows)
                 rp += row_bytes;
         }
     };
@@ -279,7 +285,7 @@ __device__ __forceinline__ void fir_block(
         for (int i = tid; i < se - sa; i += FIR_THREADS) {
             int c;
             double tau;
-            s_c[i] = split_delay(ds[sa + i], D, c, tau) ? c : -1;
+            s_c[i] = split_delay(ds[sa + i - moff], D, c, tau) ? c : -1;
         }
         __syncthreads();
 
@@ -301,7 +307,7 @@ __device__ __forceinline__ void fir_block(
                     acc = fmaf(float(sample_at(rs, hs, i, H)), h[j], acc);
                     i += n2;
                 }
-                store_f32(c >= 0 ? acc : 0.f, rg, t_bytes, uint32_t(m * n2 * 4));
+                store_f32(c >= 0 ? acc : 0.f, rg, t_bytes, uint32_t((m - moff) * n2 * 4));
                 c_cur = -1;                                   // X holds no rows
                 ++m;
                 continue;
@@ -356,7 +362,7 @@ __device__ __forceinline__ void fir_block(
                     pend[r] = acc;
                 }
                 pend_cnt = min(T, send - g0);
-                pend_soff = uint32_t(g0 * n2 * 4);
+                pend_soff = uint32_t((g0 - moff) * n2 * 4);
                 // rows g0+1 .. g0+T-1 become the older rows of the next group
 #pragma unroll
                 for (int i = 0; i < T - 1; ++i)
@@ -377,11 +383,33 @@ __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
-    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me)
+    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
+    int moff, int mrows)
 {
     __shared__ int s_c[FIR_SEG];            // coarse delay of each spectrum of the segment, -1 if invalid
     fir_block<T>(xcd_logical(blockIdx.x, gridDim.x), s_c, raw, raw_stride, hist, hist_stride, H, taps,
-                 delays, g, n2, M, D, R, colblocks, runs, mb, me);
+                 delays, g, n2, M, D, R, colblocks, runs, mb, me, moff, mrows);
+}
+
+// The seam of a call for the FIR: per stream, dst = [zero bytes | the
+// history (hist_bytes) | the chunk's first head_bytes], as 32-bit words (all
+// sizes and offsets are multiples of 4 bytes).
+__global__ void seam_stage_kernel(uint32_t *__restrict__ dst, int64_t dst_words,
+                                  const uint32_t *__restrict__ hist, int64_t hist_words,
+                                  const uint32_t *__restrict__ raw, int64_t raw_words,
+                                  int64_t zero_words, int64_t head_words, int streams)
+{
+    const int64_t total = dst_words * streams;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t s = e / dst_words, i = e % dst_words;
+        uint32_t v = 0u;
+        if (i >= zero_words && i < zero_words + hist_words)
+            v = hist[s * hist_words + (i - zero_words)];
+        else if (i >= zero_words + hist_words && i < zero_words + hist_words + head_words)
+            v = raw[s * raw_words + (i - zero_words - hist_words)];
+        dst[e] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1051,7 +1079,7 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw_sub, const float2 *__restrict__ untangle,
     uint32_t *__restrict__ spec8, float2 *__restrict__ y_out, int *__restrict__ status,
-    int M, int D, int mb, int me)
+    int M, int D, int mb, int me, int rparts)
 {
     constexpr int NS = NL / 16;                             // sub-transform length
     constexpr int NTS = NS / 16;                            // threads per sub-transform
@@ -1061,7 +1089,12 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
     __shared__ float2 ph_hi[NH];
     __shared__ float2 ph_lo[64];
 
-    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    // block = (work item, part): the nine rounds of a spectrum are split over
+    // rparts workgroups, so that a call of few spectra still fills the GPU
+    const int lb = xcd_logical(blockIdx.x, gridDim.x);
+    const int item = lb / rparts, part = lb % rparts;
+    const int rper = (9 + rparts - 1) / rparts;
+    const int dd0 = part * rper, dd1 = min(9, dd0 + rper);
     const int p = item & 1;
     const int af = item >> 1;
     const int a = af / (me - mb);
@@ -1076,11 +1109,11 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
     int c;
     double tau;
     const bool ok = split_delay(delays[sp], D, c, tau);
-    if (!ok && tid == 0)
+    if (!ok && tid == 0 && part == 0)
         atomicOr(status, 1);
     phase_tables<NL, NT>(ph_hi, ph_lo, phases[sp], tau, 0.5f, tid);
 
-    for (int dd = 0; dd <= 8; ++dd) {
+    for (int dd = dd0; dd < dd1; ++dd) {
         const int dsel = half == 0 ? dd : (16 - dd) & 15;
         float2 *bh = buf[half];
         float2 v[16];
@@ -1998,6 +2031,113 @@ __global__ __launch_bounds__(256) void corner_turn_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Batches: kernels driven by job lists spanning the member streams, so that
+// a batch step runs one FIR launch per tap count, one FFT/post launch per
+// channel count and one corner-turn launch for all its FP32 members.  Job j
+// owns blocks [begin_j, begin_{j+1}) (the list is in block order); a block
+// finds its job by a scan of the (at most a few dozen) entries, which every
+// lane reads alike.
+// ---------------------------------------------------------------------------
+
+struct FirJob {
+    const uint8_t *raw;
+    int64_t raw_stride;
+    const uint8_t *hist;
+    int64_t hist_stride;
+    const float *taps;
+    const double *delays;
+    float *g;
+    int H, n2, M, D, R, colblocks, runs, mb, me, moff, mrows, begin;
+};
+
+struct PostJob {
+    const float *g;
+    const double *delays;
+    const double *phases;
+    const float2 *gains;
+    const float2 *tw;
+    const float2 *untangle;
+    uint32_t *spec8;
+    int *status;
+    int M, D, begin, pad;
+};
+
+struct TurnJob {
+    const uint32_t *spec8;
+    int8_t *out;
+    int M, n, S, ftiles, ktiles, ns, begin, pad;
+};
+
+// per stream s < streams: dst[s dst_stride + i], i < len (32-bit words) =
+// 0 for i < z, src1[s src1_stride + i - z] for i < z + h, else
+// src2[s src2_stride + src2_off + i - z - h]; the job owns words
+// [begin, begin + streams len) of the launch
+struct CopyJob {
+    uint32_t *dst;
+    const uint32_t *src1;
+    const uint32_t *src2;
+    int64_t dst_stride, src1_stride, src2_stride, src2_off, z, h, len, begin;
+    int streams, pad;
+};
+
+template <typename J>
+__device__ __forceinline__ int find_job(const J *__restrict__ jobs, int njobs, int64_t b)
+{
+    int j = 0;
+    while (j + 1 < njobs && jobs[j + 1].begin <= b)
+        ++j;
+    return j;
+}
+
+template <int T>
+__global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_jobs_kernel(const FirJob *__restrict__ jobs,
+                                                                                  int njobs)
+{
+    __shared__ int s_c[FIR_SEG];
+    const int b = blockIdx.x;
+    const FirJob &J = jobs[find_job(jobs, njobs, b)];
+    fir_block<T>(b - J.begin, s_c, J.raw, J.raw_stride, J.hist, J.hist_stride, J.H, J.taps, J.delays, J.g, J.n2,
+                 J.M, J.D, J.R, J.colblocks, J.runs, J.mb, J.me, J.moff, J.mrows);
+}
+
+template <int N>
+__global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void post_jobs_kernel(const PostJob *__restrict__ jobs,
+                                                                                    int njobs)
+{
+    constexpr int NH = N / 64;
+    __shared__ float2 buf[lds_len<N>()];
+    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[64];
+    const int b = blockIdx.x;
+    const PostJob &J = jobs[find_job(jobs, njobs, b)];
+    fft_post_block<N, OUT_INT8>(b - J.begin, true, threadIdx.x, buf, ph_hi, ph_lo, J.g, J.delays, J.phases,
+                                J.gains, J.tw, J.untangle, J.spec8, nullptr, J.status, J.M, J.D, 0, J.M);
+}
+
+__global__ __launch_bounds__(256) void turn_jobs_kernel(const TurnJob *__restrict__ jobs, int njobs)
+{
+    __shared__ uint16_t t16[CT][2 * CT + 2];
+    const int b = blockIdx.x;
+    const TurnJob &J = jobs[find_job(jobs, njobs, b)];
+    corner_turn_block(b - J.begin, 0, t16, J.spec8, J.out, J.M, J.n, J.S, J.ftiles, J.ktiles, J.ns);
+}
+
+__global__ void copy_jobs_kernel(const CopyJob *__restrict__ jobs, int njobs, int64_t total)
+{
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const CopyJob &J = jobs[find_job(jobs, njobs, e)];
+        const int64_t w = e - J.begin, s = w / J.len, i = w % J.len;
+        uint32_t v = 0u;
+        if (i >= J.z && i < J.z + J.h)
+            v = J.src1[s * J.src1_stride + (i - J.z)];
+        else if (i >= J.z + J.h)
+            v = J.src2[s * J.src2_stride + J.src2_off + (i - J.z - J.h)];
+        J.dst[s * J.dst_stride + i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // History maintenance and small helpers
 // ---------------------------------------------------------------------------
 
@@ -2077,6 +2217,7 @@ struct fe_stream {
     uint32_t *d_dfta;       // DFT-16 A-operand images [K half][hi, lo][lane][8 x 16 bit]
     uint8_t *d_hist;        // [A*2][H*5/4]
     uint8_t *d_hist_tmp;    // same, used when a call is shorter than H
+    uint8_t *d_seam;        // FP32: staging of the FIR's seam, seam_bytes()
     float *d_g;             // [A*2][max_samples/(2n)][2n]
     uint32_t *d_spec8;      // [A*2][max_samples/(2n)][n] (re, im) int8 pairs
     int *d_status;
@@ -2263,14 +2404,35 @@ struct Work {
     uint32_t *spec8;        // int8 spectra before the corner turn
     float2 *gpl;            // n > 8192: the call's gains in residue-plane order
     uint8_t *hist_tmp;      // history assembly for calls shorter than H
+    uint8_t *seam;          // FP32 FIR: the history's tail and the chunk's first rows
 };
 
+unsigned grid_for(int64_t work, int threads)
+{
+    int64_t b = (work + threads - 1) / threads;
+    if (b < 1)
+        b = 1;
+    if (b > 65536)
+        b = 65536;
+    return unsigned(b);
+}
+
+// The FIR's seam: the first T' - 1 + ceil(D / 2n) spectra of a call read
+// rows before it (the history).  They are filtered from a staging buffer of
+// ceil(H / 2n) history rows followed by the chunk's first rows, on the same
+// grouped fast path as the rest of the call.
+int seam_rows_before(const fe_stream *s) { return (s->H + 2 * s->n - 1) / (2 * s->n); }
+int seam_spectra(const fe_stream *s) { return s->Tk - 1 + (s->D + 2 * s->n - 1) / (2 * s->n); }
+int64_t seam_bytes(const fe_stream *s)
+{
+    return int64_t(2 * s->A) * (seam_rows_before(s) + seam_spectra(s)) * (int64_t(2 * s->n) * 5 / 4);
+}
+
 template <int T>
-void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g,
-                  int mb, int me)
+void launch_fir_range(const fe_stream *s, const uint8_t *raw, int64_t raw_stride, int mrows, int moff, int M,
+                      const double *delays, float *g, int mb, int me)
 {
     const int n2 = 2 * s->n;
-    const int M = int(N / n2);
     const int streams = 2 * s->A;
     const int colblocks = n2 / FIR_THREADS;
     // runs of R spectra (whole batches of B = (64/T)T); longer runs load the
@@ -2285,8 +2447,36 @@ void launch_fir_T(const fe_stream *s, const uint8_t *raw, int64_t N, const doubl
     const int runs = (me - mb + R - 1) / R;
     const int64_t blocks = int64_t(streams) * runs * colblocks;
     hipLaunchKernelGGL((fir_kernel<T>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
-                       raw, N * 5 / 4, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps, delays, g,
-                       n2, M, s->D, R, colblocks, runs, mb, me);
+                       raw, raw_stride, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps, delays, g,
+                       n2, M, s->D, R, colblocks, runs, mb, me, moff, mrows);
+}
+
+template <int T>
+void launch_fir_T(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays,
+                  float *g, int mb, int me)
+{
+    const int n2 = 2 * s->n;
+    const int M = int(N / n2);
+    const int S0 = std::min(me, seam_spectra(s));
+    int main_mb = mb;
+    if (mb < S0) {
+        const int K = seam_rows_before(s);
+        const int rows = K + S0;
+        const int64_t row_bytes = int64_t(n2) * 5 / 4;             // a multiple of 4
+        const int64_t dst_words = rows * row_bytes / 4;
+        const int64_t zero_words = (int64_t(K) * n2 - s->H) * 5 / 16;
+        const int64_t hist_words = int64_t(s->H) * 5 / 16;
+        const int streams = 2 * s->A;
+        hipLaunchKernelGGL(seam_stage_kernel, dim3(grid_for(dst_words * streams, 256)), dim3(256), 0, s->stream,
+                           reinterpret_cast<uint32_t *>(wk.seam), dst_words,
+                           reinterpret_cast<const uint32_t *>(s->d_hist), hist_words,
+                           reinterpret_cast<const uint32_t *>(raw), N * 5 / 16, zero_words,
+                           int64_t(S0) * row_bytes / 4, streams);
+        launch_fir_range<T>(s, wk.seam, rows * row_bytes, rows, K, M, delays, g, K + mb, K + S0);
+        main_mb = S0;
+    }
+    if (main_mb < me)
+        launch_fir_range<T>(s, raw, N * 5 / 4, M, 0, M, delays, g, main_mb, me);
 }
 
 template <int TK, int PREC>
@@ -2315,7 +2505,7 @@ void launch_fir_mfma_T(const fe_stream *s, const uint8_t *raw, int64_t N, const 
                            s->tap_scale, s->out_scale, delays, g, n2, M, s->D, mb, me, ctiles, ftiles, chain);
 }
 
-void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double *delays, float *g,
+void launch_fir(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays, float *g,
                 int mb, int me, bool g_out = false)
 {
     if (s->prec != FE_PREC_FP32) {
@@ -2333,11 +2523,11 @@ void launch_fir(const fe_stream *s, const uint8_t *raw, int64_t N, const double 
         return;
     }
     switch (s->Tk) {
-    case 4: launch_fir_T<4>(s, raw, N, delays, g, mb, me); break;
-    case 8: launch_fir_T<8>(s, raw, N, delays, g, mb, me); break;
-    case 16: launch_fir_T<16>(s, raw, N, delays, g, mb, me); break;
-    case 24: launch_fir_T<24>(s, raw, N, delays, g, mb, me); break;
-    case 32: launch_fir_T<32>(s, raw, N, delays, g, mb, me); break;
+    case 4: launch_fir_T<4>(s, wk, raw, N, delays, g, mb, me); break;
+    case 8: launch_fir_T<8>(s, wk, raw, N, delays, g, mb, me); break;
+    case 16: launch_fir_T<16>(s, wk, raw, N, delays, g, mb, me); break;
+    case 24: launch_fir_T<24>(s, wk, raw, N, delays, g, mb, me); break;
+    case 32: launch_fir_T<32>(s, wk, raw, N, delays, g, mb, me); break;
     }
 }
 
@@ -2397,17 +2587,21 @@ void launch_post_large(const fe_stream *s, const Work &wk, int M, const double *
     const int64_t fthreads = int64_t(s->A) * 2 * (me - mb) * (NL / 16);
     hipLaunchKernelGGL(fft_front_kernel, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0, s->stream,
                        wk.g, s->d_twf, reinterpret_cast<const float2 *>(gains), wk.gpl, NL, M, mb, me, s->A);
-    const unsigned blocks = unsigned(s->A * (me - mb) * 2);
+    // the nine rounds of each spectrum over 9 workgroups for calls of few
+    // spectra, over 3 otherwise
+    const int items = s->A * (me - mb) * 2;
+    const int rparts = items < 4096 ? 9 : 3;
+    const unsigned blocks = unsigned(items * rparts);
     if (y_out)
         hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_PREQUANT>), dim3(blocks), dim3(NL / 128), 0,
                            s->stream, wk.g, delays, phases, wk.gpl, s->d_tw,
                            s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
-                           mb, me);
+                           mb, me, rparts);
     else
         hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_INT8>), dim3(blocks), dim3(NL / 128), 0,
                            s->stream, wk.g, delays, phases, wk.gpl, s->d_tw,
                            s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
-                           mb, me);
+                           mb, me, rparts);
 }
 
 void launch_post(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
@@ -2532,16 +2726,6 @@ void launch_corner_turn(const fe_stream *s, const Work &wk, int M, int8_t *out)
                        s->stream, wk.spec8, out, M, s->n, s->S, ftiles, ktiles, ns);
 }
 
-unsigned grid_for(int64_t work, int threads)
-{
-    int64_t b = (work + threads - 1) / threads;
-    if (b < 1)
-        b = 1;
-    if (b > 65536)
-        b = 65536;
-    return unsigned(b);
-}
-
 void launch_history_update(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N)
 {
     const int streams = 2 * s->A;
@@ -2576,18 +2760,22 @@ fe_status check_call(const fe_stream *s, const uint8_t *raw, int64_t N, const do
 
 // Bytes of static scratch a call of N samples needs (fe_channelize_noalloc):
 // the regions of Work, each rounded up to 256 bytes.
-int64_t scratch_need(const fe_stream *s, int64_t N, int64_t *off_spec8, int64_t *off_gpl, int64_t *off_hist)
+int64_t scratch_need(const fe_stream *s, int64_t N, int64_t *off_spec8, int64_t *off_gpl, int64_t *off_hist,
+                     int64_t *off_seam)
 {
     auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
     const int64_t streams = 2 * int64_t(s->A);
-    const int64_t g = fused_path(s) ? 0 : up(streams * N * 4);
+    const bool fused = fused_path(s);
+    const int64_t g = fused ? 0 : up(streams * N * 4);
     const int64_t spec8 = up(streams * N);
     const int64_t gpl = s->n > 8192 ? up(streams * s->n * 8) : 0;
     const int64_t hist = N < s->H ? up(streams * (int64_t(s->H) * 5 / 4)) : 0;
+    const int64_t seam = s->prec == FE_PREC_FP32 && !fused ? up(seam_bytes(s)) : 0;
     *off_spec8 = g;
     *off_gpl = g + spec8;
     *off_hist = g + spec8 + gpl;
-    return g + spec8 + gpl + hist;
+    *off_seam = g + spec8 + gpl + hist;
+    return g + spec8 + gpl + hist + seam;
 }
 
 fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const double *delays,
@@ -2599,16 +2787,17 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
         return st;
     if (!g_out && (!phases || !gains || (!out && !y_out)))
         return FE_EINVAL;
-    Work wk = {s->d_g, s->d_spec8, s->d_gpl, s->d_hist_tmp};
+    Work wk = {s->d_g, s->d_spec8, s->d_gpl, s->d_hist_tmp, s->d_seam};
     if (scratch_base) {
         // the static scratch in place of the stream's workspace
-        int64_t o_spec8, o_gpl, o_hist;
-        if (scratch_need(s, N, &o_spec8, &o_gpl, &o_hist) > int64_t(FE_NOALLOC_SCRATCH_BYTES))
+        int64_t o_spec8, o_gpl, o_hist, o_seam;
+        if (scratch_need(s, N, &o_spec8, &o_gpl, &o_hist, &o_seam) > int64_t(FE_NOALLOC_SCRATCH_BYTES))
             return FE_ESIZE;
         wk.g = reinterpret_cast<float *>(scratch_base);
         wk.spec8 = reinterpret_cast<uint32_t *>(scratch_base + o_spec8);
         wk.gpl = reinterpret_cast<float2 *>(scratch_base + o_gpl);
         wk.hist_tmp = scratch_base + o_hist;
+        wk.seam = scratch_base + o_seam;
     }
     int cur = -1;
     if (hipGetDevice(&cur) != hipSuccess)
@@ -2629,7 +2818,7 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
     if (fused)
         launch_fused(s, wk, raw, N, delays, phases, gains, y_out, g_out, 0, M);
     else
-        launch_fir(s, raw, N, delays, g_out ? g_out : wk.g, 0, M, g_out != nullptr);
+        launch_fir(s, wk, raw, N, delays, g_out ? g_out : wk.g, 0, M, g_out != nullptr);
     mark(1);
     launch_history_update(s, wk, raw, N);
     mark(2);
@@ -2668,6 +2857,7 @@ void free_stream(fe_stream *s)
     (void)hipFree(s->d_dfta);
     (void)hipFree(s->d_hist);
     (void)hipFree(s->d_hist_tmp);
+    (void)hipFree(s->d_seam);
     (void)hipFree(s->d_g);
     (void)hipFree(s->d_spec8);
     (void)hipFree(s->d_status);
@@ -2770,6 +2960,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
               && (n <= 8192 || hipMalloc(&s->d_gpl, size_t(streams) * n * sizeof(float2)) == hipSuccess)
               && hipMalloc(&s->d_hist, hist_bytes) == hipSuccess
               && hipMalloc(&s->d_hist_tmp, hist_bytes) == hipSuccess
+              && (s->prec != FE_PREC_FP32 || hipMalloc(&s->d_seam, size_t(seam_bytes(s))) == hipSuccess)
               && hipMalloc(&s->d_g, g_floats * sizeof(float)) == hipSuccess
               && hipMalloc(&s->d_spec8, size_t(streams) * size_t(cfg->max_samples)) == hipSuccess
               && hipMalloc(&s->d_status, sizeof(int)) == hipSuccess;
@@ -3075,6 +3266,15 @@ struct fe_batch {
     hipEvent_t fork_ev;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    // job tables of the grouped launches: one for the captured graph, one for
+    // eager runs (uploaded from pinned host memory on the batch stream)
+    size_t jobs_cap;                       // bytes of each table
+    uint8_t *d_jobs_graph;
+    uint8_t *d_jobs_eager;
+    uint8_t *h_jobs;
+    hipEvent_t upload_ev;
+    bool upload_pending;
+    bool grouped;                          // grouped launches (else every member on its fork stream)
 };
 
 namespace {
@@ -3083,6 +3283,12 @@ void free_batch(fe_batch *b)
 {
     if (!b)
         return;
+    (void)hipFree(b->d_jobs_graph);
+    (void)hipFree(b->d_jobs_eager);
+    if (b->h_jobs)
+        (void)hipHostFree(b->h_jobs);
+    if (b->upload_ev)
+        (void)hipEventDestroy(b->upload_ev);
     if (b->exec)
         (void)hipGraphExecDestroy(b->exec);
     if (b->graph)
@@ -3098,6 +3304,281 @@ void free_batch(fe_batch *b)
     if (b->cap)
         (void)hipStreamDestroy(b->cap);
     delete b;
+}
+
+// Members run by the grouped launches: FP32 streams on the split path.
+bool grouped_member(const fe_stream *s) { return s->prec == FE_PREC_FP32 && !fused_path(s); }
+
+// Job tables of one batch step and the launches that read them (offsets into
+// one byte table).
+struct BatchPlan {
+    std::vector<uint8_t> table;
+    struct Launch {
+        int kind;                          // 0 copy, 1 FIR (by taps), 2 FFT/post (by n), 3 turn
+        int param;                         // taps or n
+        size_t off;
+        int count;
+        int64_t units;                     // blocks (copy: words)
+    };
+    std::vector<Launch> pre, mid, post;    // before the FIR (seam staging), FIR + history, FFT/post + turn
+    std::vector<int> short_calls;          // members whose call is shorter than their history
+    std::vector<int> large;                // members with n > 8192 (their FFT runs per member)
+};
+
+template <typename J>
+void plan_add(BatchPlan &P, std::vector<BatchPlan::Launch> &list, int kind, int param, const std::vector<J> &jobs,
+              int64_t units)
+{
+    if (jobs.empty())
+        return;
+    size_t off = (P.table.size() + 63) / 64 * 64;
+    P.table.resize(off + jobs.size() * sizeof(J));
+    std::memcpy(P.table.data() + off, jobs.data(), jobs.size() * sizeof(J));
+    list.push_back({kind, param, off, int(jobs.size()), units});
+}
+
+// FIR run length over `spectra` spectra (as launch_fir_range)
+int fir_run_length(const fe_stream *s, int T, int spectra)
+{
+    const int streams = 2 * s->A, colblocks = 2 * s->n / FIR_THREADS, B = (64 / T) * T;
+    if (s->fir_batches > 0)
+        return s->fir_batches * B;
+    int R = 4 * B;
+    while (R > B && int64_t(streams) * ((spectra + R - 1) / R) * colblocks < 2048)
+        R -= B;
+    return R;
+}
+
+void build_plan(const fe_batch *b, const fe_call *calls, BatchPlan &P)
+{
+    std::vector<CopyJob> stage, hist;
+    int64_t stage_w = 0, hist_w = 0;
+    static const int taps_k[] = {4, 8, 16, 24, 32};
+    static const int ns_k[] = {256, 512, 1024, 2048, 4096, 8192};
+    std::vector<FirJob> fir[5];
+    int64_t fir_b[5] = {0, 0, 0, 0, 0};
+    std::vector<PostJob> post[6];
+    int64_t post_b[6] = {0, 0, 0, 0, 0, 0};
+    std::vector<TurnJob> turn;
+    int64_t turn_b = 0;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        const fe_stream *s = b->members[i];
+        if (!grouped_member(s))
+            continue;
+        const fe_call &c = calls[i];
+        const int64_t N = c.n_samples;
+        const int n2 = 2 * s->n, M = int(N / n2), streams = 2 * s->A, T = s->Tk;
+        const int64_t row_bytes = int64_t(n2) * 5 / 4, hb = int64_t(s->H) * 5 / 4, nb = N * 5 / 4;
+        const int ti = int(std::find(taps_k, taps_k + 5, T) - taps_k);
+        FirJob F = {};
+        F.hist = s->d_hist;
+        F.hist_stride = hb;
+        F.taps = s->d_taps;
+        F.delays = c.delays;
+        F.g = s->d_g;
+        F.H = s->H;
+        F.n2 = n2;
+        F.M = M;
+        F.D = s->D;
+        F.colblocks = n2 / FIR_THREADS;
+        // the seam from a staging buffer, the rest from the chunk
+        const int S0 = std::min(M, seam_spectra(s)), K = seam_rows_before(s), rows = K + S0;
+        CopyJob C = {};
+        C.dst = reinterpret_cast<uint32_t *>(s->d_seam);
+        C.dst_stride = rows * row_bytes / 4;
+        C.src1 = reinterpret_cast<const uint32_t *>(s->d_hist);
+        C.src1_stride = hb / 4;
+        C.src2 = reinterpret_cast<const uint32_t *>(c.raw);
+        C.src2_stride = nb / 4;
+        C.z = (int64_t(K) * n2 - s->H) * 5 / 16;
+        C.h = hb / 4;
+        C.len = rows * row_bytes / 4;
+        C.streams = streams;
+        C.begin = stage_w;
+        stage_w += C.len * streams;
+        stage.push_back(C);
+        F.raw = s->d_seam;
+        F.raw_stride = rows * row_bytes;
+        F.mb = K;
+        F.me = K + S0;
+        F.moff = K;
+        F.mrows = rows;
+        F.R = fir_run_length(s, T, S0);
+        F.runs = (S0 + F.R - 1) / F.R;
+        F.begin = int(fir_b[ti]);
+        fir_b[ti] += int64_t(streams) * F.runs * F.colblocks;
+        fir[ti].push_back(F);
+        if (S0 < M) {
+            F.raw = c.raw;
+            F.raw_stride = nb;
+            F.mb = S0;
+            F.me = M;
+            F.moff = 0;
+            F.mrows = M;
+            F.R = fir_run_length(s, T, M - S0);
+            F.runs = (M - S0 + F.R - 1) / F.R;
+            F.begin = int(fir_b[ti]);
+            fir_b[ti] += int64_t(streams) * F.runs * F.colblocks;
+            fir[ti].push_back(F);
+        }
+        // the history: the chunk's last H samples (shorter calls per member)
+        if (N >= s->H) {
+            CopyJob Hj = {};
+            Hj.dst = reinterpret_cast<uint32_t *>(s->d_hist);
+            Hj.dst_stride = hb / 4;
+            Hj.src2 = reinterpret_cast<const uint32_t *>(c.raw);
+            Hj.src2_stride = nb / 4;
+            Hj.src2_off = (nb - hb) / 4;
+            Hj.len = hb / 4;
+            Hj.streams = streams;
+            Hj.begin = hist_w;
+            hist_w += Hj.len * streams;
+            hist.push_back(Hj);
+        } else {
+            P.short_calls.push_back(int(i));
+        }
+        if (s->n > 8192) {
+            P.large.push_back(int(i));
+        } else {
+            const int ni = int(std::find(ns_k, ns_k + 6, s->n) - ns_k);
+            PostJob Q = {};
+            Q.g = s->d_g;
+            Q.delays = c.delays;
+            Q.phases = c.phases;
+            Q.gains = reinterpret_cast<const float2 *>(c.gains);
+            Q.tw = s->d_tw;
+            Q.untangle = s->d_untangle;
+            Q.spec8 = s->d_spec8;
+            Q.status = s->d_status;
+            Q.M = M;
+            Q.D = s->D;
+            Q.begin = int(post_b[ni]);
+            post_b[ni] += int64_t(s->A) * M * 2;
+            post[ni].push_back(Q);
+        }
+        TurnJob U = {};
+        U.spec8 = s->d_spec8;
+        U.out = c.out;
+        U.M = M;
+        U.n = s->n;
+        U.S = s->S;
+        U.ftiles = (M + CT - 1) / CT;
+        U.ktiles = s->n / CT;
+        U.ns = s->n > 8192 ? s->n / 16 : 0;
+        U.begin = int(turn_b);
+        turn_b += int64_t(s->A) * U.ftiles * U.ktiles;
+        turn.push_back(U);
+    }
+    plan_add(P, P.pre, 0, 0, stage, stage_w);
+    for (int t = 0; t < 5; ++t)
+        plan_add(P, P.mid, 1, taps_k[t], fir[t], fir_b[t]);
+    plan_add(P, P.mid, 0, 0, hist, hist_w);
+    for (int k = 0; k < 6; ++k)
+        plan_add(P, P.post, 2, ns_k[k], post[k], post_b[k]);
+    plan_add(P, P.post, 3, 0, turn, turn_b);
+}
+
+void launch_plan_list(const std::vector<BatchPlan::Launch> &list, const uint8_t *table, hipStream_t st)
+{
+    for (const BatchPlan::Launch &L : list) {
+        const void *j = table + L.off;
+        const unsigned blocks = unsigned(L.units);
+        switch (L.kind) {
+        case 0:
+            hipLaunchKernelGGL(copy_jobs_kernel, dim3(grid_for(L.units, 256)), dim3(256), 0, st,
+                               static_cast<const CopyJob *>(j), L.count, L.units);
+            break;
+        case 1: {
+            const FirJob *f = static_cast<const FirJob *>(j);
+            switch (L.param) {
+            case 4: hipLaunchKernelGGL((fir_jobs_kernel<4>), dim3(blocks), dim3(FIR_THREADS), 0, st, f, L.count); break;
+            case 8: hipLaunchKernelGGL((fir_jobs_kernel<8>), dim3(blocks), dim3(FIR_THREADS), 0, st, f, L.count); break;
+            case 16: hipLaunchKernelGGL((fir_jobs_kernel<16>), dim3(blocks), dim3(FIR_THREADS), 0, st, f, L.count); break;
+            case 24: hipLaunchKernelGGL((fir_jobs_kernel<24>), dim3(blocks), dim3(FIR_THREADS), 0, st, f, L.count); break;
+            case 32: hipLaunchKernelGGL((fir_jobs_kernel<32>), dim3(blocks), dim3(FIR_THREADS), 0, st, f, L.count); break;
+            }
+            break;
+        }
+        case 2: {
+            const PostJob *q = static_cast<const PostJob *>(j);
+            switch (L.param) {
+            case 256: hipLaunchKernelGGL((post_jobs_kernel<256>), dim3(blocks), dim3(256 / 16), 0, st, q, L.count); break;
+            case 512: hipLaunchKernelGGL((post_jobs_kernel<512>), dim3(blocks), dim3(512 / 16), 0, st, q, L.count); break;
+            case 1024: hipLaunchKernelGGL((post_jobs_kernel<1024>), dim3(blocks), dim3(1024 / 16), 0, st, q, L.count); break;
+            case 2048: hipLaunchKernelGGL((post_jobs_kernel<2048>), dim3(blocks), dim3(2048 / 16), 0, st, q, L.count); break;
+            case 4096: hipLaunchKernelGGL((post_jobs_kernel<4096>), dim3(blocks), dim3(4096 / 16), 0, st, q, L.count); break;
+            case 8192: hipLaunchKernelGGL((post_jobs_kernel<8192>), dim3(blocks), dim3(8192 / 16), 0, st, q, L.count); break;
+            }
+            break;
+        }
+        case 3:
+            hipLaunchKernelGGL(turn_jobs_kernel, dim3(blocks), dim3(256), 0, st, static_cast<const TurnJob *>(j),
+                               L.count);
+            break;
+        }
+    }
+}
+
+// Enqueue one step: the members outside the grouped launches (fused-path and
+// matrix-core streams) each on a fork stream of their own; the FP32 split
+// members through the grouped launches on the origin stream (job table
+// `table`, device, already holding plan P's jobs); then the origin stream
+// waits for the forks.
+fe_status batch_enqueue_grouped(fe_batch *b, const fe_call *calls, hipStream_t origin, const BatchPlan &P,
+                                const uint8_t *table)
+{
+    if (hipEventRecord(b->fork_ev, origin) != hipSuccess)
+        return FE_EHIP;
+    fe_status st = FE_OK;
+    std::vector<size_t> forked;
+    for (size_t i = 0; i < b->members.size() && st == FE_OK; ++i) {
+        fe_stream *m = b->members[i];
+        if (grouped_member(m))
+            continue;
+        const fe_call &c = calls[i];
+        if (hipStreamWaitEvent(b->forks[i], b->fork_ev, 0) != hipSuccess)
+            return FE_EHIP;
+        hipStream_t saved = m->stream;
+        const bool timing = m->timing;
+        m->stream = b->forks[i];
+        m->timing = false;
+        st = channelize_impl(m, c.raw, c.n_samples, c.delays, c.phases, c.gains, c.out, nullptr, nullptr);
+        m->stream = saved;
+        m->timing = timing;
+        if (st == FE_OK && hipEventRecord(b->join[i], b->forks[i]) != hipSuccess)
+            st = FE_EHIP;
+        forked.push_back(i);
+    }
+    if (st == FE_OK) {
+        (void)hipGetLastError();
+        launch_plan_list(P.pre, table, origin);
+        launch_plan_list(P.mid, table, origin);
+        // per member: history of calls shorter than it, FFT of n > 8192
+        for (int i : P.short_calls) {
+            fe_stream *m = b->members[size_t(i)];
+            const Work wk = {m->d_g, m->d_spec8, m->d_gpl, m->d_hist_tmp, m->d_seam};
+            hipStream_t saved = m->stream;
+            m->stream = origin;
+            launch_history_update(m, wk, calls[i].raw, calls[i].n_samples);
+            m->stream = saved;
+        }
+        for (int i : P.large) {
+            fe_stream *m = b->members[size_t(i)];
+            const fe_call &c = calls[i];
+            const Work wk = {m->d_g, m->d_spec8, m->d_gpl, m->d_hist_tmp, m->d_seam};
+            const int M = int(c.n_samples / (2 * m->n));
+            hipStream_t saved = m->stream;
+            m->stream = origin;
+            launch_post(m, wk, M, c.delays, c.phases, c.gains, nullptr, 0, M);
+            m->stream = saved;
+        }
+        launch_plan_list(P.post, table, origin);
+        st = hip_status(hipGetLastError());
+    }
+    for (size_t i : forked)
+        if (hipStreamWaitEvent(origin, b->join[i], 0) != hipSuccess && st == FE_OK)
+            st = FE_EHIP;
+    return st;
 }
 
 // Enqueue every member's call: the fork streams wait for the batch stream,
@@ -3166,7 +3647,17 @@ fe_status fe_batch_create(fe_stream *const *members, int count, void *hip_stream
     b->graph = nullptr;
     b->exec = nullptr;
     b->cap = nullptr;
+    b->d_jobs_graph = b->d_jobs_eager = b->h_jobs = nullptr;
+    b->upload_ev = nullptr;
+    b->upload_pending = false;
+    b->grouped = true;
+    b->jobs_cap = size_t(count) * (2 * sizeof(FirJob) + sizeof(PostJob) + sizeof(TurnJob) + 2 * sizeof(CopyJob))
+                  + 64 * 16;
     bool ok = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess
+              && hipEventCreateWithFlags(&b->upload_ev, hipEventDisableTiming) == hipSuccess
+              && hipMalloc(&b->d_jobs_graph, b->jobs_cap) == hipSuccess
+              && hipMalloc(&b->d_jobs_eager, b->jobs_cap) == hipSuccess
+              && hipHostMalloc(&b->h_jobs, b->jobs_cap, hipHostMallocDefault) == hipSuccess
               && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; i < count && ok; ++i)
         ok = hipStreamCreateWithFlags(&b->forks[size_t(i)], hipStreamNonBlocking) == hipSuccess
@@ -3198,7 +3689,31 @@ fe_status fe_batch_run(fe_batch *b, const fe_call *calls)
     fe_status st = batch_check(b, calls);
     if (st != FE_OK)
         return st;
-    return batch_enqueue(b, calls, b->main);
+    if (!b->grouped)
+        return batch_enqueue(b, calls, b->main);
+    BatchPlan P;
+    build_plan(b, calls, P);
+    if (P.table.size() > b->jobs_cap)
+        return FE_EINVAL;
+    // the pinned staging is rewritten once its last upload has been read
+    if (b->upload_pending && hipEventSynchronize(b->upload_ev) != hipSuccess)
+        return FE_EHIP;
+    if (!P.table.empty()) {
+        std::memcpy(b->h_jobs, P.table.data(), P.table.size());
+        if (hipMemcpyAsync(b->d_jobs_eager, b->h_jobs, P.table.size(), hipMemcpyHostToDevice, b->main) != hipSuccess
+            || hipEventRecord(b->upload_ev, b->main) != hipSuccess)
+            return FE_EHIP;
+        b->upload_pending = true;
+    }
+    return batch_enqueue_grouped(b, calls, b->main, P, b->d_jobs_eager);
+}
+
+fe_status fe_batch_set_grouped(fe_batch *b, int grouped)
+{
+    if (!b)
+        return FE_EINVAL;
+    b->grouped = grouped != 0;
+    return FE_OK;
 }
 
 fe_status fe_batch_capture(fe_batch *b, const fe_call *calls)
@@ -3216,9 +3731,19 @@ fe_status fe_batch_capture(fe_batch *b, const fe_call *calls)
         (void)hipGraphDestroy(b->graph);
         b->graph = nullptr;
     }
+    BatchPlan P;
+    if (b->grouped) {
+        // the graph's job table is written once, before the capture
+        build_plan(b, calls, P);
+        if (P.table.size() > b->jobs_cap)
+            return FE_EINVAL;
+        if (!P.table.empty()
+            && hipMemcpy(b->d_jobs_graph, P.table.data(), P.table.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return FE_EHIP;
+    }
     if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return FE_EHIP;
-    st = batch_enqueue(b, calls, b->cap);
+    st = b->grouped ? batch_enqueue_grouped(b, calls, b->cap, P, b->d_jobs_graph) : batch_enqueue(b, calls, b->cap);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(b->cap, &g);
     if (st != FE_OK || ec != hipSuccess || !g) {

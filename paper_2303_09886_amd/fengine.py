@@ -97,6 +97,8 @@ def load_library(path: Optional[str] = None):
         f.restype = _st
     L.fe_batch_launch.argtypes = [_vp]
     L.fe_batch_launch.restype = _st
+    L.fe_batch_set_grouped.argtypes = [_vp, ctypes.c_int]
+    L.fe_batch_set_grouped.restype = _st
     L.fe_debug_unpack10.argtypes = [_vp, _i64, _i64, _vp, _vp]
     L.fe_debug_unpack10.restype = _st
     L.fe_strerror.argtypes = [_st]
@@ -353,6 +355,10 @@ class Batch:
 
     def launch(self):
         _check(load_library().fe_batch_launch(self._h), "fe_batch_launch")
+
+    def set_grouped(self, grouped: bool):
+        """fe_batch_set_grouped: grouped launches (default) or every member on its own fork stream."""
+        _check(load_library().fe_batch_set_grouped(self._h, 1 if grouped else 0), "fe_batch_set_grouped")
 
     def close(self):
         if getattr(self, "_h", None):

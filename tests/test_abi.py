@@ -109,6 +109,7 @@ def test_batch_and_tuning_reject_bad_arguments(lib):
     assert lib.fe_batch_run(None, None) == fe.FE_EINVAL
     assert lib.fe_batch_capture(None, None) == fe.FE_EINVAL
     assert lib.fe_batch_destroy(None) == fe.FE_OK
+    assert lib.fe_batch_set_grouped(None, 1) == fe.FE_EINVAL
     dummy = ctypes.c_void_p(0x1000)
     assert lib.fe_stream_autotune(None, dummy, 1 << 20, dummy, dummy, dummy, dummy, 1, None) == fe.FE_EINVAL
     assert lib.fe_stream_set_tuning(None, 1) == fe.FE_EINVAL
