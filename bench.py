@@ -256,20 +256,51 @@ def measure_service(chunks: int = 24, seed: int = 3):
             reqs.append(service.Request(0, raw, N, d, p, g_pin, arrival=t, out=out))
         return reqs
 
+    # the same chunks already in device memory (input and output): the
+    # device side of the service without the host link
+    raw_dev, d_dev, p_dev, g_dev = (raw_pin.cuda(), d_pin.cuda(), p_pin.cuda(), g_pin.cuda())
+
+    ks_dev = rng.integers(1, 33, size=64)                 # more chunks: device memory holds them
+
+    def resident(rate):
+        reqs, t = [], 0.0
+        for k in ks_dev:
+            N = int(k) * unit
+            s0 = int(rng.integers(0, 33 - k))
+            raw = raw_dev[:, s0 * unit * 5 // 4:(s0 + k) * unit * 5 // 4].contiguous()
+            d = d_dev[:, s0 * spu:(s0 + k) * spu].contiguous()
+            p = p_dev[:, s0 * spu:(s0 + k) * spu].contiguous()
+            M = N // (2 * sh.n)
+            out = torch.empty((1, M // sh.spectra_per_heap, sh.n, sh.spectra_per_heap, 2, 2), dtype=torch.int8,
+                              device="cuda")
+            if rate:
+                t += rng.exponential(N * 2 / rate)
+            reqs.append(service.Request(0, raw, N, d, p, g_dev, arrival=t, out=out))
+        torch.cuda.synchronize()
+        return reqs
+
     budget = 4 * service.chunk_device_bytes(sh.n, 32 * unit)
     res = {}
-    for mode in ("backlog", "arrivals"):
-        svc = service.Service(sh.n, sh.taps, base.weights, feeds=1, max_chunk_samples=32 * unit,
-                              hbm_budget=budget, spectra_per_heap=sh.spectra_per_heap)
-        svc.run(requests(0), realtime=False)                 # warm-up (allocator, pinned slots)
-        rate = 0.7 * res["backlog"]["gsamples_per_s"] * 1e9 if mode == "arrivals" else 0
-        r = svc.run(requests(rate), realtime=(mode == "arrivals"))
-        svc.close()
-        res[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
-        if rate:
-            res[mode]["offered_gsamples_per_s"] = round(rate / 1e9, 3)
+    for kind, make in (("host", requests), ("device_resident", resident)):
+        legs = {}
+        for mode in ("backlog", "arrivals"):
+            svc = service.Service(sh.n, sh.taps, base.weights, feeds=1, max_chunk_samples=32 * unit,
+                                  hbm_budget=budget, spectra_per_heap=sh.spectra_per_heap)
+            svc.run(make(0), realtime=False)                 # warm-up (allocator, pinned slots)
+            rate = 0.7 * legs["backlog"]["gsamples_per_s"] * 1e9 if mode == "arrivals" else 0
+            r = svc.run(make(rate), realtime=(mode == "arrivals"))
+            svc.close()
+            legs[mode] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+            if rate:
+                legs[mode]["offered_gsamples_per_s"] = round(rate / 1e9, 3)
+        if kind == "host":
+            res.update(legs)                                 # backlog / arrivals: host memory in and out
+        else:
+            res[kind] = legs
     res["config"] = ("1 antenna x 2 pols, 32768 channels (65536-pt real FFT), 16 taps, chunks of k*2^20 "
-                     "samples/pol with k uniform in 1..32, heaps of 16 spectra, HBM budget %d MB"
+                     "samples/pol with k uniform in 1..32, heaps of 16 spectra, HBM budget %d MB; backlog and "
+                     "arrivals: chunks in pinned host memory, heaps back to pinned host memory; "
+                     "device_resident: the same chunks and their outputs in device memory"
                      % (budget >> 20))
     return res
 

@@ -12,8 +12,11 @@ next to the work already in flight; it is then copied to the device and
 channelized on its feed's own HIP stream.  Different feeds' chunks therefore
 run concurrently on the GPU, chunks that arrive while others run join as
 memory frees up, and a feed's chunks queue behind each other on its stream.
-Completion is detected with HIP events; the int8 heaps come back to pinned
-host memory.  Latency = completion time - arrival time.
+Completion is event-driven: a thread per feed blocks on its oldest chunk's
+HIP event and releases the chunk's memory; the int8 heaps come back to
+pinned host memory, or stay on the device when the request brought device
+buffers (input and output already in HBM: the device-side figures).
+Latency = completion time - arrival time.
 
 All channelizer arithmetic runs in the library's HIP kernels; this module
 schedules, moves buffers and keeps time.
@@ -41,7 +44,9 @@ class Request:
     """One chunk of one feed.
 
     raw     uint8 [2][N*5/4] packed 10-bit samples (host: a numpy array, or
-            a pinned torch tensor, which is copied to the device directly)
+            a pinned torch tensor, which is copied to the device directly;
+            or, with every other buffer including ``out``, a device tensor:
+            the chunk is then channelized in place, nothing is copied)
     delays  float64 [2][M], phases float64 [2][M]  (M = N / 2n)
     gains   float32 [2][n][2]
     arrival seconds on the loop's clock (0 = loop start)
@@ -113,6 +118,14 @@ class Service:
         N = r.n_samples
         M = N // (2 * self.n)
         nb = 2 * N * 5 // 4
+        if self._resident(r):
+            # everything already in device memory: the call alone
+            self.streams[f].channelize(r.raw, N, r.delays, r.phases, r.gains, r.out)
+            ev = torch.cuda.Event()
+            ev.record(self.hip[f])
+            r.admitted = now
+            return {"req": r, "event": ev, "keep": None, "slot": slot, "own": True,
+                    "shape": tuple(r.out.shape), "bytes": self.chunk_bytes(N)}
         # host side: chunks that already sit in pinned host memory (torch
         # tensors, as a receive ring would hold them) are copied straight to
         # the device; others go through the pinned staging slot first
@@ -145,10 +158,23 @@ class Service:
         return {"req": r, "event": ev, "keep": (raw, d, ph, g, out), "slot": slot, "own": own,
                 "shape": tuple(out.shape), "bytes": self.chunk_bytes(N)}
 
-    def run(self, requests: List[Request], realtime: bool = True, poll: float = 20e-6) -> Dict:
+    def _resident(self, r: Request) -> bool:
+        """A request whose buffers are all device tensors (output included)."""
+        torch = self.torch
+        return all(isinstance(a, torch.Tensor) and a.is_cuda for a in (r.raw, r.delays, r.phases, r.gains, r.out))
+
+    def run(self, requests: List[Request], realtime: bool = True) -> Dict:
         """Serve ``requests`` (sorted by arrival).  ``realtime``: admit a
         request no earlier than its arrival time; otherwise all arrive at 0.
-        Returns throughput and latency statistics; outputs land in req.out."""
+        Returns throughput and latency statistics; outputs land in req.out.
+
+        Completion is event-driven: one thread per feed blocks on the HIP
+        event of its feed's oldest chunk in flight (a feed's chunks finish in
+        order) and then releases the chunk's memory; the admitting loop
+        sleeps on a condition variable until a chunk arrives or memory frees
+        up."""
+        import threading
+        import queue
         for r in requests:
             if r.n_samples % (2 * self.n * self.S) or r.n_samples > self.max_chunk:
                 raise ValueError("chunk of %d samples does not fit the service" % r.n_samples)
@@ -158,39 +184,64 @@ class Service:
         if not realtime:
             for r in pending:
                 r.arrival = 0.0
-        inflight = []
-        used = 0
-        peak = 0
+        cond = threading.Condition()
+        state = {"used": 0, "inflight": 0, "peak": 0, "error": None}
+        queues = [queue.Queue() for _ in self.streams]
         t0 = time.perf_counter()
-        i = 0
-        while i < len(pending) or inflight:
-            now = time.perf_counter() - t0
-            # retire finished chunks (any order across feeds)
-            still = []
-            for job in inflight:
-                if job["event"].query():
+
+        def complete(f):
+            while True:
+                job = queues[f].get()
+                if job is None:
+                    return
+                try:
+                    job["event"].synchronize()                 # blocks without the interpreter lock
                     r = job["req"]
                     r.done = time.perf_counter() - t0
-                    k = 2 * r.n_samples
                     if not job["own"]:
+                        k = 2 * r.n_samples
                         r.out = job["slot"]["out"][:k].numpy().reshape(job["shape"]).copy()
-                    self.slots.append(job["slot"])
-                    used -= job["bytes"]
-                else:
-                    still.append(job)
-            inflight = still
-            # admit arrivals in order while the budget allows
-            while i < len(pending) and pending[i].arrival <= now:
-                need = self.chunk_bytes(pending[i].n_samples)
-                if used + need > self.budget or len(inflight) >= self.host_slots:
-                    break
-                inflight.append(self._start(pending[i], now, self._slot()))
-                used += need
-                peak = max(peak, used)
-                i += 1
-            if inflight or (i < len(pending) and pending[i].arrival > now):
-                time.sleep(poll)
-        wall = time.perf_counter() - t0
+                except Exception as e:                         # reported by run()
+                    state["error"] = e
+                with cond:
+                    if job["slot"] is not None:
+                        self.slots.append(job["slot"])
+                    state["used"] -= job["bytes"]
+                    state["inflight"] -= 1
+                    cond.notify_all()
+
+        threads = [threading.Thread(target=complete, args=(f,), daemon=True) for f in range(len(self.streams))]
+        for t in threads:
+            t.start()
+        try:
+            for r in pending:
+                need = self.chunk_bytes(r.n_samples)
+                resident = self._resident(r)
+                with cond:
+                    while True:
+                        if state["error"] is not None:
+                            raise state["error"]
+                        now = time.perf_counter() - t0
+                        if r.arrival > now:
+                            cond.wait(timeout=r.arrival - now)
+                            continue
+                        if state["used"] + need > self.budget or (not resident and state["inflight"] >= self.host_slots):
+                            cond.wait()
+                            continue
+                        state["used"] += need
+                        state["inflight"] += 1
+                        state["peak"] = max(state["peak"], state["used"])
+                        break
+                job = self._start(r, time.perf_counter() - t0, None if resident else self._slot_locked(cond))
+                queues[r.feed].put(job)
+        finally:
+            for q in queues:
+                q.put(None)
+            for t in threads:
+                t.join()
+        if state["error"] is not None:
+            raise state["error"]
+        wall = max(r.done for r in requests) if requests else 0.0
         lat = np.array([r.latency for r in requests]) * 1e3
         samples = 2 * sum(r.n_samples for r in requests)
         for st in self.streams:
@@ -200,7 +251,11 @@ class Service:
                 "gsamples_per_s": samples / wall / 1e9,
                 "latency_ms_p50": float(np.percentile(lat, 50)),
                 "latency_ms_p99": float(np.percentile(lat, 99)),
-                "latency_ms_max": float(lat.max()), "peak_inflight_bytes": peak}
+                "latency_ms_max": float(lat.max()), "peak_inflight_bytes": state["peak"]}
+
+    def _slot_locked(self, cond):
+        with cond:
+            return self._slot()
 
     def close(self):
         for st in self.streams:

@@ -2,7 +2,8 @@
 
 * every feed's chunks, served mixed with other feeds' chunks under an HBM
   budget, come back bit-identical to the same chunks run alone through a
-  plain stream (state carried on the device between chunks);
+  plain stream (state carried on the device between chunks), whether they
+  come from host memory or already sit in device memory;
 * the served output matches the FP64 oracle on sampled spectra.
 """
 import sys
@@ -53,6 +54,11 @@ def feeds_and_requests(n, T, S, feeds, chunks, kmax, seed):
 
 def alone(works, reqs, n, T, S, max_chunk):
     outs = {}
+    reqs = [service.Request(r.feed, r.raw.cpu().numpy()[0] if torch.is_tensor(r.raw) else r.raw, r.n_samples,
+                            r.delays.cpu().numpy()[0] if torch.is_tensor(r.delays) else r.delays,
+                            r.phases.cpu().numpy()[0] if torch.is_tensor(r.phases) else r.phases,
+                            r.gains.cpu().numpy()[0] if torch.is_tensor(r.gains) else r.gains)
+            for r in reqs]
     for f, w in enumerate(works):
         st = fe.Stream(n, T, 1, w.weights, max_chunk, spectra_per_heap=S)
         for i, r in enumerate(reqs):
@@ -69,14 +75,24 @@ def alone(works, reqs, n, T, S, max_chunk):
     return outs
 
 
-@pytest.mark.parametrize("realtime,own_out", [(False, False), (True, False), (False, True)])
+@pytest.mark.parametrize("realtime,own_out", [(False, False), (True, False), (False, True),
+                                               (False, "device"), (True, "device")])
 def test_mixed_equals_alone(realtime, own_out):
     """own_out: the requests bring pinned output buffers (filled by the
-    device directly instead of through the service's staging slots)."""
+    device directly instead of through the service's staging slots);
+    "device": every buffer of the request, output included, is already in
+    device memory (the device-resident service)."""
     n, T, S = 32768, 16, 16
     unit = 2 * n * S
     works, reqs = feeds_and_requests(n, T, S, feeds=3, chunks=4, kmax=3, seed=7)
-    if own_out:
+    if own_out == "device":
+        dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        for r in reqs:
+            M = r.n_samples // (2 * n)
+            r.raw, r.delays, r.phases, r.gains = dv(r.raw[None]), dv(r.delays[None]), dv(r.phases[None]), \
+                dv(r.gains[None])
+            r.out = torch.empty((1, M // S, n, S, 2, 2), dtype=torch.int8, device="cuda")
+    elif own_out:
         for r in reqs:
             r.out = torch.empty(2 * r.n_samples, dtype=torch.int8).pin_memory()
     max_chunk = 3 * unit
@@ -90,7 +106,10 @@ def test_mixed_equals_alone(realtime, own_out):
          % ("arrivals" if realtime else "backlog", stats["chunks"], stats["gsamples_per_s"],
             stats["latency_ms_p50"], stats["latency_ms_p99"], stats["peak_inflight_bytes"] / 1e6))
     for i, r in enumerate(reqs):
-        got = r.out.numpy().reshape(ref[i].shape) if own_out else r.out
+        if own_out == "device":
+            got = r.out.cpu().numpy()
+        else:
+            got = r.out.numpy().reshape(ref[i].shape) if own_out else r.out
         assert got is not None and np.array_equal(got, ref[i]), i
     assert stats["peak_inflight_bytes"] <= budget
 
