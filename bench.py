@@ -40,6 +40,13 @@ HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, published
 FP32_PEAK_TFLOPS = 157.3        # MI355X FP32 vector, published
 METRIC = "Gsample/s channelized on 1 GPU (FP32 vs FP16-MFMA) + % HBM roofline"
 PATH_BYTES_PER_SAMPLE = 2.25    # 10-bit in + int8 complex out, per real sample
+# Delay slopes of the timed workloads: the sidereal rate of Sec. 3.3 (below
+# 3e-9 samples per sample), so the coarse delay of a call is (nearly)
+# constant; the parity tests and the small workload use 1e-5, whose integer
+# part steps many times inside one call, and the benchmark reports that
+# slope for the large workload as a variant.
+SIDEREAL_RATE = 3e-9
+DRIFT_RATE = 1e-5
 
 
 def log(*a):
@@ -152,7 +159,7 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True):
     shapes = synth.BATCH16
     streams, bufs = [], []
     for i, sh in enumerate(shapes):
-        w = synth.make_workload(sh, 100 + i)
+        w = synth.make_workload(sh, 100 + i, delay_rate=SIDEREAL_RATE)
         M = sh.samples // (2 * sh.n)
         st = fe.Stream(sh.n, sh.taps, 1, w.weights, sh.samples, spectra_per_heap=sh.spectra_per_heap,
                        max_delay=sh.max_delay)
@@ -225,7 +232,8 @@ def measure_service(chunks: int = 24, seed: int = 3):
     sh = synth.STREAM32K
     unit = sh.samples                                  # 2^20 samples = 32 spectra
     base = synth.make_workload(synth.Shape(n=sh.n, taps=sh.taps, antennas=1, samples=32 * unit,
-                                           spectra_per_heap=sh.spectra_per_heap), seed)
+                                           spectra_per_heap=sh.spectra_per_heap), seed,
+                               delay_rate=SIDEREAL_RATE)
     rng = np.random.default_rng(seed)
     ks = rng.integers(1, 33, size=chunks)
     import torch
@@ -394,9 +402,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=None,
                     help="spectra per antenna for the CPU baseline (default: all)")
-    ap.add_argument("--variants", default="fp16,bf16,fused",
+    ap.add_argument("--variants", default="fp16,bf16,fused,drift",
                     help="variants timed beside the FP32 path: fp16, bf16 (matrix cores), split, fused "
-                         "(the FP32 stream on those kernel paths); comma list, empty for none")
+                         "(the FP32 stream on those kernel paths), drift (delays drifting at 1e-5 "
+                         "samples/sample); comma list, empty for none")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-stream batch measurement")
     ap.add_argument("--no-service", action="store_true", help="skip the streaming-service measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -421,7 +430,7 @@ def main():
     N, A, n, S = shape.samples, shape.antennas, shape.n, shape.spectra_per_heap
     M = N // (2 * n)
     log("generating workload: %s" % (shape,))
-    w = synth.make_workload(shape, 2)
+    w = synth.make_workload(shape, 2, delay_rate=SIDEREAL_RATE)
 
     dev = torch.device("cuda:0")
     raw0 = torch.from_numpy(w.raw).to(dev)
@@ -439,6 +448,14 @@ def main():
     res = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup)
     variants = {}
     for prec in args.variants.split(",") if args.variants else []:
+        if prec == "drift":
+            # the large workload with delays drifting at 1e-5 samples/sample
+            wd = synth.make_workload(shape, 2, delay_rate=DRIFT_RATE)
+            dd = torch.from_numpy(wd.delays).to(dev)
+            variants["fp32_delay_drift_1e-5"] = measure(fe, shape, wd, sets, (dd, phases, gains), "fp32",
+                                                        args.steps, args.warmup)
+            del wd, dd
+            continue
         if prec in ("fused", "split"):
             # the same FP32 stream on another kernel path (fe_stream_set_schedule)
             variants["fp32_" + prec] = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup,

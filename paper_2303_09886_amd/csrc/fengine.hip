@@ -3275,6 +3275,9 @@ struct fe_batch {
     hipEvent_t upload_ev;
     bool upload_pending;
     bool grouped;                          // grouped launches (else every member on its fork stream)
+    hipStream_t gs[6];                     // grouped launches: one stream per FIR / FFT group
+    hipEvent_t gev[6];
+    hipEvent_t fir_done;
 };
 
 namespace {
@@ -3283,6 +3286,14 @@ void free_batch(fe_batch *b)
 {
     if (!b)
         return;
+    for (int k = 0; k < 6; ++k) {
+        if (b->gs[k])
+            (void)hipStreamDestroy(b->gs[k]);
+        if (b->gev[k])
+            (void)hipEventDestroy(b->gev[k]);
+    }
+    if (b->fir_done)
+        (void)hipEventDestroy(b->fir_done);
     (void)hipFree(b->d_jobs_graph);
     (void)hipFree(b->d_jobs_eager);
     if (b->h_jobs)
@@ -3550,10 +3561,46 @@ fe_status batch_enqueue_grouped(fe_batch *b, const fe_call *calls, hipStream_t o
         forked.push_back(i);
     }
     if (st == FE_OK) {
+        // seam staging on the origin stream; then each FIR group (one per
+        // tap count) on a group stream of its own; once all have finished,
+        // the history copies on the origin stream beside each FFT group (one
+        // per channel count) and each large-n member's two-level FFT on
+        // streams of their own; the corner turn after all of them
         (void)hipGetLastError();
         launch_plan_list(P.pre, table, origin);
-        launch_plan_list(P.mid, table, origin);
-        // per member: history of calls shorter than it, FFT of n > 8192
+        bool ok = hipEventRecord(b->fir_done, origin) == hipSuccess;
+        std::vector<BatchPlan::Launch> firs, hists, posts, turns;
+        for (const BatchPlan::Launch &L : P.mid)
+            (L.kind == 1 ? firs : hists).push_back(L);
+        for (const BatchPlan::Launch &L : P.post)
+            (L.kind == 2 ? posts : turns).push_back(L);
+        for (size_t k = 0; k < firs.size() && ok; ++k) {
+            ok = hipStreamWaitEvent(b->gs[k], b->fir_done, 0) == hipSuccess;
+            launch_plan_list(std::vector<BatchPlan::Launch>(1, firs[k]), table, b->gs[k]);
+            ok = ok && hipEventRecord(b->gev[k], b->gs[k]) == hipSuccess
+                 && hipStreamWaitEvent(origin, b->gev[k], 0) == hipSuccess;
+        }
+        ok = ok && hipEventRecord(b->fir_done, origin) == hipSuccess;
+        for (size_t k = 0; k < posts.size() && ok; ++k) {
+            ok = hipStreamWaitEvent(b->gs[k], b->fir_done, 0) == hipSuccess;
+            launch_plan_list(std::vector<BatchPlan::Launch>(1, posts[k]), table, b->gs[k]);
+            ok = ok && hipEventRecord(b->gev[k], b->gs[k]) == hipSuccess;
+        }
+        for (int i : P.large) {
+            if (!ok)
+                break;
+            fe_stream *m = b->members[size_t(i)];
+            const fe_call &c = calls[i];
+            const Work wk = {m->d_g, m->d_spec8, m->d_gpl, m->d_hist_tmp, m->d_seam};
+            const int M = int(c.n_samples / (2 * m->n));
+            ok = hipStreamWaitEvent(b->forks[size_t(i)], b->fir_done, 0) == hipSuccess;
+            hipStream_t saved = m->stream;
+            m->stream = b->forks[size_t(i)];
+            launch_post(m, wk, M, c.delays, c.phases, c.gains, nullptr, 0, M);
+            m->stream = saved;
+            ok = ok && hipEventRecord(b->join[size_t(i)], b->forks[size_t(i)]) == hipSuccess;
+        }
+        launch_plan_list(hists, table, origin);
         for (int i : P.short_calls) {
             fe_stream *m = b->members[size_t(i)];
             const Work wk = {m->d_g, m->d_spec8, m->d_gpl, m->d_hist_tmp, m->d_seam};
@@ -3562,18 +3609,12 @@ fe_status batch_enqueue_grouped(fe_batch *b, const fe_call *calls, hipStream_t o
             launch_history_update(m, wk, calls[i].raw, calls[i].n_samples);
             m->stream = saved;
         }
-        for (int i : P.large) {
-            fe_stream *m = b->members[size_t(i)];
-            const fe_call &c = calls[i];
-            const Work wk = {m->d_g, m->d_spec8, m->d_gpl, m->d_hist_tmp, m->d_seam};
-            const int M = int(c.n_samples / (2 * m->n));
-            hipStream_t saved = m->stream;
-            m->stream = origin;
-            launch_post(m, wk, M, c.delays, c.phases, c.gains, nullptr, 0, M);
-            m->stream = saved;
-        }
-        launch_plan_list(P.post, table, origin);
-        st = hip_status(hipGetLastError());
+        for (size_t k = 0; k < posts.size() && ok; ++k)
+            ok = hipStreamWaitEvent(origin, b->gev[k], 0) == hipSuccess;
+        for (int i : P.large)
+            ok = ok && hipStreamWaitEvent(origin, b->join[size_t(i)], 0) == hipSuccess;
+        launch_plan_list(turns, table, origin);
+        st = ok ? hip_status(hipGetLastError()) : FE_EHIP;
     }
     for (size_t i : forked)
         if (hipStreamWaitEvent(origin, b->join[i], 0) != hipSuccess && st == FE_OK)
@@ -3651,6 +3692,11 @@ fe_status fe_batch_create(fe_stream *const *members, int count, void *hip_stream
     b->upload_ev = nullptr;
     b->upload_pending = false;
     b->grouped = true;
+    for (int k = 0; k < 6; ++k) {
+        b->gs[k] = nullptr;
+        b->gev[k] = nullptr;
+    }
+    b->fir_done = nullptr;
     b->jobs_cap = size_t(count) * (2 * sizeof(FirJob) + sizeof(PostJob) + sizeof(TurnJob) + 2 * sizeof(CopyJob))
                   + 64 * 16;
     bool ok = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess
@@ -3658,7 +3704,11 @@ fe_status fe_batch_create(fe_stream *const *members, int count, void *hip_stream
               && hipMalloc(&b->d_jobs_graph, b->jobs_cap) == hipSuccess
               && hipMalloc(&b->d_jobs_eager, b->jobs_cap) == hipSuccess
               && hipHostMalloc(&b->h_jobs, b->jobs_cap, hipHostMallocDefault) == hipSuccess
-              && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+              && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess
+              && hipEventCreateWithFlags(&b->fir_done, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 6 && ok; ++k)
+        ok = hipStreamCreateWithFlags(&b->gs[k], hipStreamNonBlocking) == hipSuccess
+             && hipEventCreateWithFlags(&b->gev[k], hipEventDisableTiming) == hipSuccess;
     for (int i = 0; i < count && ok; ++i)
         ok = hipStreamCreateWithFlags(&b->forks[size_t(i)], hipStreamNonBlocking) == hipSuccess
              && hipEventCreateWithFlags(&b->join[size_t(i)], hipEventDisableTiming) == hipSuccess;
@@ -3678,6 +3728,9 @@ fe_status fe_batch_destroy(fe_batch *b)
     if (b->cap && hipStreamSynchronize(b->cap) != hipSuccess)
         st = FE_EHIP;
     for (hipStream_t f : b->forks)
+        if (f && hipStreamSynchronize(f) != hipSuccess)
+            st = FE_EHIP;
+    for (hipStream_t f : b->gs)
         if (f && hipStreamSynchronize(f) != hipSuccess)
             st = FE_EHIP;
     free_batch(b);
