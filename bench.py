@@ -72,8 +72,9 @@ def kernel_names(shape: synth.Shape, prec: str, path: str = "split"):
             return {"fir": "pfb_fused_kernel<%d,%d>" % (n, tk), "turn": "corner_turn_kernel"}
         return {"fir": "fir_kernel<%d>" % tk, "post": "fft_post_kernel<%d>" % n, "turn": "corner_turn_kernel"}
     tk = 16 if T <= 16 else 32
-    return {"fir": "fir_mfma_kernel<%d,%s>" % (tk, prec), "post": "fft_mfma_kernel<%d,%s>" % (n, prec),
-            "turn": "corner_turn_kernel"}
+    fir = ("fir_mfma_kernel<%d,%s>" % (tk, prec) if path == "matrix_fir"
+           else "fir_kernel<%d,%s>" % (tk, "fp16-out" if prec == "fp16" else "fp32-out"))
+    return {"fir": fir, "post": "fft_mfma_kernel<%d,%s>" % (n, prec), "turn": "corner_turn_kernel"}
 
 
 def measure(fe, shape, w, sets, dev_arrays, prec, steps, warmup, path="auto"):
@@ -402,10 +403,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=None,
                     help="spectra per antenna for the CPU baseline (default: all)")
-    ap.add_argument("--variants", default="fp16,bf16,fused,drift",
-                    help="variants timed beside the FP32 path: fp16, bf16 (matrix cores), split, fused "
-                         "(the FP32 stream on those kernel paths), drift (delays drifting at 1e-5 "
-                         "samples/sample); comma list, empty for none")
+    ap.add_argument("--variants", default="fp16,bf16,fp16_matrix_fir,fused,drift",
+                    help="variants timed beside the FP32 path: fp16, bf16 (DFT stages on the matrix "
+                         "cores, vector FIR), fp16_matrix_fir, bf16_matrix_fir (FIR on the matrix cores "
+                         "too), split, fused (the FP32 stream on those kernel paths), drift (delays "
+                         "drifting at 1e-5 samples/sample); comma list, empty for none")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-stream batch measurement")
     ap.add_argument("--no-service", action="store_true", help="skip the streaming-service measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -455,6 +457,11 @@ def main():
             variants["fp32_delay_drift_1e-5"] = measure(fe, shape, wd, sets, (dd, phases, gains), "fp32",
                                                         args.steps, args.warmup)
             del wd, dd
+            continue
+        if prec in ("fp16_matrix_fir", "bf16_matrix_fir"):
+            # the reduced-precision stream with its FIR on the matrix cores
+            variants[prec] = measure(fe, shape, w, sets, dev_arrays, prec[:4], args.steps, args.warmup,
+                                     path="matrix_fir")
             continue
         if prec in ("fused", "split"):
             # the same FP32 stream on another kernel path (fe_stream_set_schedule)

@@ -206,8 +206,10 @@ fe_status fe_debug_unpack10(const uint8_t *raw, int64_t first, int64_t count,
 
 /* Time the stream's launch choices on the caller's buffers (an fe_channelize
  * call's arguments; `iters` timed calls per candidate, HIP events on the
- * stream's HIP stream) and keep the fastest.  Where the stream can run both
- * paths (fe_stream_set_schedule) each is timed, and the faster kept.  The
+ * stream's HIP stream) and keep the fastest.  Where an FP32 stream can run
+ * both the split and the fused path (fe_stream_set_schedule) each is timed,
+ * and the faster kept; their results are identical bit for bit.  The FIR
+ * engine of an FP16/BF16 stream is not changed (it changes the rounding).  The
  * candidates set the FIR's schedule: for FP32 streams its run length -- how many consecutive batches
  * of spectra one workgroup filters (a batch is 64 spectra, 48 for 24 taps),
  * trading tap reloads against parallelism; for FP16/BF16 streams the chain
@@ -228,7 +230,7 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
 fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches);
 
 /* Kernels of the path (fe_stream_set_schedule). */
-enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2 };
+enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2, FE_PATH_MATRIX_FIR = 3 };
 
 /* Choose the kernels that run a stream's calls, and the FIR schedule.
  * FE_PATH_SPLIT: a FIR kernel (steps 1-3a) writes the filtered samples as
@@ -238,8 +240,15 @@ enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2 };
  *   filters four consecutive spectra of a polarization into on-chip memory
  *   and transforms and finishes them there; no filtered sample is written to
  *   device memory.  Then the corner turn.
- * FE_PATH_AUTO: fused for T <= 8 and n <= 2048, else split (the faster of the
- *   two on MI355X for those shapes).
+ * FE_PATH_MATRIX_FIR (FP16/BF16 streams only): the split path with the FIR
+ *   on the matrix cores as a banded Toeplitz contraction (16 consecutive
+ *   spectra of a column per v_mfma_f32_16x16x32, taps in FP16 or BF16
+ *   hi + lo).  Otherwise FP16/BF16 streams filter on the vector ALUs in
+ *   float32 and store the filtered samples as FP16 (FP16 streams) or float32
+ *   (BF16 streams) for the matrix-core DFT stages.
+ * FE_PATH_AUTO: fused for FP32 streams with T <= 8 and n <= 2048, else split
+ *   (the fastest on MI355X for those shapes; for FP16/BF16 streams the
+ *   vector FIR).
  * Streams the fused path cannot run always run the split path (the setting
  * is kept).  fir_batches as in fe_stream_set_tuning; on the fused path it
  * caps the kernel's workgroups per compute unit (0 = as many as fit).
@@ -247,8 +256,9 @@ enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2 };
  * fir_batches outside 0..64. */
 fe_status fe_stream_set_schedule(fe_stream *s, int path, int fir_batches);
 
-/* The path the stream's calls run now (FE_PATH_SPLIT or FE_PATH_FUSED) and
- * its fir_batches setting.  Either pointer may be NULL. */
+/* The path the stream's calls run now (FE_PATH_SPLIT, FE_PATH_FUSED or
+ * FE_PATH_MATRIX_FIR) and its fir_batches setting.  Either pointer may be
+ * NULL. */
 fe_status fe_stream_get_schedule(const fe_stream *s, int *path, int *fir_batches);
 
 /* ---- Batches of streams ------------------------------------------------ */

@@ -162,6 +162,23 @@ __device__ __forceinline__ void store_f32(float v, __amdgpu_buffer_rsrc_t r, uin
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 2);
 }
 
+// How the FIR stores its filtered samples g: float32 (FP32 and BF16 streams),
+// FP16 (FP16 streams: the matrix-core FFT's operand), or float32 holding the
+// FP16-rounded value (FP16 streams' FIR-stage debug output).
+enum { G_F32 = 0, G_F16 = 1, G_F32_AS_F16 = 2 };
+
+template <int GM>
+__device__ __forceinline__ void store_g(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    if constexpr (GM == G_F16) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)v), r, voff, soff, 2);
+    } else {
+        if constexpr (GM == G_F32_AS_F16)
+            v = float((_Float16)v);
+        store_f32(v, r, voff, soff);
+    }
+}
+
 // Unaligned 16-bit global load (little-endian) at byte `off` of a
 // wave-uniform base in the global address space (so the address is an SGPR
 // pair plus one 32-bit VGPR).
@@ -190,15 +207,16 @@ __device__ __forceinline__ float field10(uint32_t u, uint32_t lo_shift)
 // call (its delay and its filtered samples).  The call's own chunk has
 // moff = 0, mrows = M; a staged seam (the history's tail and the chunk's first
 // rows, one buffer per stream) has moff = its rows before the chunk.
-template <int T>
+template <int T, int GM = G_F32>
 __device__ __forceinline__ void fir_block(
     int lb, int *__restrict__ s_c,
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
-    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
+    void *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
     int moff, int mrows)
 {
+    constexpr uint32_t ES = GM == G_F16 ? 2u : 4u;          // bytes per stored sample
     const int cb = lb % colblocks;
     const int rest = lb / colblocks;
     const int run = rest % runs;
@@ -217,10 +235,10 @@ __device__ __forceinline__ void fir_block(
     const double *ds = delays + int64_t(s) * M;
     const uint8_t *rs = raw + int64_t(s) * raw_stride;
     const uint8_t *hs = hist + int64_t(s) * hist_stride;
-    float *gs = g + int64_t(s) * M * n2;
-    const __amdgpu_buffer_rsrc_t rg = make_rsrc(gs, uint32_t(int64_t(M) * n2 * 4));
+    uint8_t *gs = static_cast<uint8_t *>(g) + int64_t(s) * M * n2 * ES;
+    const __amdgpu_buffer_rsrc_t rg = make_rsrc(gs, uint32_t(int64_t(M) * n2 * ES));
     const int row_bytes = (n2 / 4) * 5;                       // 2n samples of 10 bits
-    const uint32_t t_bytes = uint32_t(t) * 4u;
+    const uint32_t t_bytes = uint32_t(t) * ES;
 
     // X: rows g0-T+1 .. g0-1 of column t at delay c_cur (raw 16-bit words
     // straight after a refill); N: the raw words of rows g0 .. g0+T-1,
@@ -274,7 +292,7 @@ __device__ __forceinline__ void fir_block(
     auto flush = [&]() {
 #pragma unroll
         for (int r = 0; r < T; ++r)
-            store_f32(pend[r], rg, t_bytes, r < pend_cnt ? pend_soff + uint32_t(r * n2 * 4) : DROP);
+            store_g<GM>(pend[r], rg, t_bytes, r < pend_cnt ? pend_soff + uint32_t(r * n2) * ES : DROP);
         pend_cnt = 0;
     };
 
@@ -307,7 +325,7 @@ __device__ __forceinline__ void fir_block(
                     acc = fmaf(float(sample_at(rs, hs, i, H)), h[j], acc);
                     i += n2;
                 }
-                store_f32(c >= 0 ? acc : 0.f, rg, t_bytes, uint32_t((m - moff) * n2 * 4));
+                store_g<GM>(c >= 0 ? acc : 0.f, rg, t_bytes, uint32_t((m - moff) * n2) * ES);
                 c_cur = -1;                                   // X holds no rows
                 ++m;
                 continue;
@@ -362,7 +380,7 @@ __device__ __forceinline__ void fir_block(
                     pend[r] = acc;
                 }
                 pend_cnt = min(T, send - g0);
-                pend_soff = uint32_t((g0 - moff) * n2 * 4);
+                pend_soff = uint32_t((g0 - moff) * n2) * ES;
                 // rows g0+1 .. g0+T-1 become the older rows of the next group
 #pragma unroll
                 for (int i = 0; i < T - 1; ++i)
@@ -378,17 +396,17 @@ __device__ __forceinline__ void fir_block(
     flush();
 }
 
-template <int T>
+template <int T, int GM>
 __global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
-    float *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
+    void *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
     int moff, int mrows)
 {
     __shared__ int s_c[FIR_SEG];            // coarse delay of each spectrum of the segment, -1 if invalid
-    fir_block<T>(xcd_logical(blockIdx.x, gridDim.x), s_c, raw, raw_stride, hist, hist_stride, H, taps,
-                 delays, g, n2, M, D, R, colblocks, runs, mb, me, moff, mrows);
+    fir_block<T, GM>(xcd_logical(blockIdx.x, gridDim.x), s_c, raw, raw_stride, hist, hist_stride, H, taps,
+                     delays, g, n2, M, D, R, colblocks, runs, mb, me, moff, mrows);
 }
 
 // The seam of a call for the FIR: per stream, dst = [zero bytes | the
@@ -2397,6 +2415,9 @@ uint8_t *scratch_address(int device)
     return g_scratch_ptr[device];
 }
 
+bool matrix_fir(const fe_stream *s);
+bool fused_path(const fe_stream *s);
+
 // Per-call intermediate buffers of a call: the stream's own workspace, or
 // the library's static scratch (fe_channelize_noalloc).
 struct Work {
@@ -2428,9 +2449,9 @@ int64_t seam_bytes(const fe_stream *s)
     return int64_t(2 * s->A) * (seam_rows_before(s) + seam_spectra(s)) * (int64_t(2 * s->n) * 5 / 4);
 }
 
-template <int T>
+template <int T, int GM>
 void launch_fir_range(const fe_stream *s, const uint8_t *raw, int64_t raw_stride, int mrows, int moff, int M,
-                      const double *delays, float *g, int mb, int me)
+                      const double *delays, void *g, int mb, int me)
 {
     const int n2 = 2 * s->n;
     const int streams = 2 * s->A;
@@ -2446,14 +2467,14 @@ void launch_fir_range(const fe_stream *s, const uint8_t *raw, int64_t raw_stride
             R -= B;
     const int runs = (me - mb + R - 1) / R;
     const int64_t blocks = int64_t(streams) * runs * colblocks;
-    hipLaunchKernelGGL((fir_kernel<T>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
+    hipLaunchKernelGGL((fir_kernel<T, GM>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
                        raw, raw_stride, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps, delays, g,
                        n2, M, s->D, R, colblocks, runs, mb, me, moff, mrows);
 }
 
-template <int T>
+template <int T, int GM>
 void launch_fir_T(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays,
-                  float *g, int mb, int me)
+                  void *g, int mb, int me)
 {
     const int n2 = 2 * s->n;
     const int M = int(N / n2);
@@ -2472,11 +2493,11 @@ void launch_fir_T(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_
                            reinterpret_cast<const uint32_t *>(s->d_hist), hist_words,
                            reinterpret_cast<const uint32_t *>(raw), N * 5 / 16, zero_words,
                            int64_t(S0) * row_bytes / 4, streams);
-        launch_fir_range<T>(s, wk.seam, rows * row_bytes, rows, K, M, delays, g, K + mb, K + S0);
+        launch_fir_range<T, GM>(s, wk.seam, rows * row_bytes, rows, K, M, delays, g, K + mb, K + S0);
         main_mb = S0;
     }
     if (main_mb < me)
-        launch_fir_range<T>(s, raw, N * 5 / 4, M, 0, M, delays, g, main_mb, me);
+        launch_fir_range<T, GM>(s, raw, N * 5 / 4, M, 0, M, delays, g, main_mb, me);
 }
 
 template <int TK, int PREC>
@@ -2505,9 +2526,34 @@ void launch_fir_mfma_T(const fe_stream *s, const uint8_t *raw, int64_t N, const 
                            s->tap_scale, s->out_scale, delays, g, n2, M, s->D, mb, me, ctiles, ftiles, chain);
 }
 
+template <int GM>
+void launch_fir_vec(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays, void *g,
+                    int mb, int me)
+{
+    switch (s->Tk) {
+    case 4: launch_fir_T<4, GM>(s, wk, raw, N, delays, g, mb, me); break;
+    case 8: launch_fir_T<8, GM>(s, wk, raw, N, delays, g, mb, me); break;
+    case 16: launch_fir_T<16, GM>(s, wk, raw, N, delays, g, mb, me); break;
+    case 24: launch_fir_T<24, GM>(s, wk, raw, N, delays, g, mb, me); break;
+    case 32: launch_fir_T<32, GM>(s, wk, raw, N, delays, g, mb, me); break;
+    }
+}
+
 void launch_fir(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays, float *g,
                 int mb, int me, bool g_out = false)
 {
+    if (s->prec != FE_PREC_FP32 && !matrix_fir(s)) {
+        // reduced-precision streams on the vector FIR: float32 arithmetic;
+        // FP16 streams store FP16 (the matrix-core FFT's operand), BF16
+        // streams float32 (their FFT splits it into hi + lo)
+        if (s->prec == FE_PREC_FP16 && g_out)
+            launch_fir_vec<G_F32_AS_F16>(s, wk, raw, N, delays, g, mb, me);
+        else if (s->prec == FE_PREC_FP16)
+            launch_fir_vec<G_F16>(s, wk, raw, N, delays, g, mb, me);
+        else
+            launch_fir_vec<G_F32>(s, wk, raw, N, delays, g, mb, me);
+        return;
+    }
     if (s->prec != FE_PREC_FP32) {
         if (s->prec == FE_PREC_FP16) {
             if (s->Tk == 16)
@@ -2522,13 +2568,7 @@ void launch_fir(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t 
         }
         return;
     }
-    switch (s->Tk) {
-    case 4: launch_fir_T<4>(s, wk, raw, N, delays, g, mb, me); break;
-    case 8: launch_fir_T<8>(s, wk, raw, N, delays, g, mb, me); break;
-    case 16: launch_fir_T<16>(s, wk, raw, N, delays, g, mb, me); break;
-    case 24: launch_fir_T<24>(s, wk, raw, N, delays, g, mb, me); break;
-    case 32: launch_fir_T<32>(s, wk, raw, N, delays, g, mb, me); break;
-    }
+    launch_fir_vec<G_F32>(s, wk, raw, N, delays, g, mb, me);
 }
 
 template <int N>
@@ -2644,9 +2684,16 @@ bool fused_eligible(const fe_stream *s)
     return s->prec == FE_PREC_FP32 && s->n <= 4096 && s->Tk <= 16;
 }
 
+// FP16/BF16 streams: the FIR on the matrix cores (the banded Toeplitz
+// contraction of fir_mfma_kernel) when chosen; by default the vector FIR
+// (float32 arithmetic), which measured faster on MI355X -- the FIR is bound
+// by memory traffic, and its Toeplitz form spends half the contraction on
+// zeros and its staging on LDS bank conflicts.
+bool matrix_fir(const fe_stream *s) { return s->prec != FE_PREC_FP32 && s->path == FE_PATH_MATRIX_FIR; }
+
 bool fused_path(const fe_stream *s)
 {
-    if (!fused_eligible(s) || s->path == FE_PATH_SPLIT)
+    if (!fused_eligible(s) || s->path == FE_PATH_SPLIT || s->path == FE_PATH_MATRIX_FIR)
         return false;
     return s->path == FE_PATH_FUSED || (s->Tk <= 8 && s->n <= 2048);
 }
@@ -2770,7 +2817,7 @@ int64_t scratch_need(const fe_stream *s, int64_t N, int64_t *off_spec8, int64_t 
     const int64_t spec8 = up(streams * N);
     const int64_t gpl = s->n > 8192 ? up(streams * s->n * 8) : 0;
     const int64_t hist = N < s->H ? up(streams * (int64_t(s->H) * 5 / 4)) : 0;
-    const int64_t seam = s->prec == FE_PREC_FP32 && !fused ? up(seam_bytes(s)) : 0;
+    const int64_t seam = !fused && !matrix_fir(s) ? up(seam_bytes(s)) : 0;
     *off_spec8 = g;
     *off_gpl = g + spec8;
     *off_hist = g + spec8 + gpl;
@@ -2960,7 +3007,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
               && (n <= 8192 || hipMalloc(&s->d_gpl, size_t(streams) * n * sizeof(float2)) == hipSuccess)
               && hipMalloc(&s->d_hist, hist_bytes) == hipSuccess
               && hipMalloc(&s->d_hist_tmp, hist_bytes) == hipSuccess
-              && (s->prec != FE_PREC_FP32 || hipMalloc(&s->d_seam, size_t(seam_bytes(s))) == hipSuccess)
+              && hipMalloc(&s->d_seam, size_t(seam_bytes(s))) == hipSuccess
               && hipMalloc(&s->d_g, g_floats * sizeof(float)) == hipSuccess
               && hipMalloc(&s->d_spec8, size_t(streams) * size_t(cfg->max_samples)) == hipSuccess
               && hipMalloc(&s->d_status, sizeof(int)) == hipSuccess;
@@ -3177,6 +3224,8 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
     // the stream can run
     static const int cand[] = {0, 1, 2, 4, 8};
     const int ncand = 5;
+    // (the FIR engine of FP16/BF16 streams is left as set: the two engines
+    // round differently, and tuning keeps results bit for bit)
     const int paths[2] = {FE_PATH_SPLIT, FE_PATH_FUSED};
     const int npaths = fused_eligible(s) ? 2 : 1;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -3237,7 +3286,8 @@ fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches)
 fe_status fe_stream_set_schedule(fe_stream *s, int path, int fir_batches)
 {
     if (!s || fir_batches < 0 || fir_batches > 64
-        || (path != FE_PATH_AUTO && path != FE_PATH_SPLIT && path != FE_PATH_FUSED))
+        || (path != FE_PATH_AUTO && path != FE_PATH_SPLIT && path != FE_PATH_FUSED
+            && path != FE_PATH_MATRIX_FIR))
         return FE_EINVAL;
     s->path = path;
     s->fir_batches = fir_batches;
@@ -3249,7 +3299,7 @@ fe_status fe_stream_get_schedule(const fe_stream *s, int *path, int *fir_batches
     if (!s)
         return FE_EINVAL;
     if (path)
-        *path = fused_path(s) ? FE_PATH_FUSED : FE_PATH_SPLIT;
+        *path = fused_path(s) ? FE_PATH_FUSED : matrix_fir(s) ? FE_PATH_MATRIX_FIR : FE_PATH_SPLIT;
     if (fir_batches)
         *fir_batches = s->fir_batches;
     return FE_OK;

@@ -18,8 +18,8 @@ FE_OK, FE_EINVAL, FE_ENOMEM, FE_EHIP, FE_EDELAY, FE_ESIZE = 0, -1, -2, -3, -4, -
 FE_NOALLOC_SCRATCH_BYTES = 64 << 20         # include/fengine.h
 FE_PREC_FP32, FE_PREC_FP16, FE_PREC_BF16 = 0, 1, 2
 PRECISIONS = {"fp32": FE_PREC_FP32, "fp16": FE_PREC_FP16, "bf16": FE_PREC_BF16}
-FE_PATH_AUTO, FE_PATH_SPLIT, FE_PATH_FUSED = 0, 1, 2
-PATHS = {"auto": FE_PATH_AUTO, "split": FE_PATH_SPLIT, "fused": FE_PATH_FUSED}
+FE_PATH_AUTO, FE_PATH_SPLIT, FE_PATH_FUSED, FE_PATH_MATRIX_FIR = 0, 1, 2, 3
+PATHS = {"auto": FE_PATH_AUTO, "split": FE_PATH_SPLIT, "fused": FE_PATH_FUSED, "matrix_fir": FE_PATH_MATRIX_FIR}
 
 
 class FEngineError(RuntimeError):
@@ -177,7 +177,7 @@ class Stream:
     ``weights`` is a host float32 array of 2n*T taps (copied at creation).
     ``precision`` is "fp32" (default), "fp16" or "bf16" (the matrix-core
     variants of the FIR and FFT, FE_PREC_* in the header).  ``path`` is
-    "auto" (default), "split" or "fused" (fe_stream_set_schedule).
+    "auto" (default), "split", "fused" or "matrix_fir" (fe_stream_set_schedule).
     Work is enqueued on ``hip_stream`` (default: torch's current stream).
     """
 
@@ -308,11 +308,12 @@ class Stream:
         _check(load_library().fe_stream_set_schedule(self._h, p, int(fir_batches)), "fe_stream_set_schedule")
 
     def schedule(self):
-        """(path that runs: "split" or "fused", fir_batches)."""
+        """(path that runs: "split", "fused" or "matrix_fir", fir_batches)."""
         p, b = ctypes.c_int(), ctypes.c_int()
         _check(load_library().fe_stream_get_schedule(self._h, ctypes.byref(p), ctypes.byref(b)),
                "fe_stream_get_schedule")
-        return ("fused" if p.value == FE_PATH_FUSED else "split"), int(b.value)
+        names = {FE_PATH_FUSED: "fused", FE_PATH_MATRIX_FIR: "matrix_fir"}
+        return names.get(p.value, "split"), int(b.value)
 
     def _call(self, raw, n_samples, delays, phases, gains, out) -> _Call:
         import torch

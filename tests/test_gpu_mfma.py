@@ -46,11 +46,27 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+# Every test runs with each FIR engine of the reduced-precision streams
+# (fe_stream_set_schedule): the vector FIR in float32 storing FP16 (FP16
+# streams) or float32 (BF16 streams) filtered samples ("split", the
+# default), and the banded Toeplitz contraction on the matrix cores
+# ("matrix_fir").  The DFT-16 stages run on the matrix cores either way.
+FIR_PATH = {"now": "split"}
+
+
+@pytest.fixture(autouse=True, params=["split", "matrix_fir"])
+def fir_engine(request):
+    FIR_PATH["now"] = request.param
+    _say("[fir %s]" % request.param)
+    yield request.param
+    FIR_PATH["now"] = "split"
+
+
 def gpu_run(w, chunk, prec, mode="int8", max_delay=128):
     s = w.shape
     A, n, S = s.antennas, s.n, s.spectra_per_heap
     st = fe.Stream(n, s.taps, A, w.weights, chunk, spectra_per_heap=S, max_delay=max_delay,
-                   precision=prec)
+                   precision=prec, path=FIR_PATH["now"])
     gains = dev(w.gains)
     outs = []
     for start in range(0, w.total, chunk):
@@ -131,13 +147,20 @@ def test_fir_impulses_fp16_bit_exact(n, T, step, M):
     w.delays[:] = np.floor(rng.uniform(0, 100, size=(A, 2, 1))) + ramp[None, None, :]
     g, status = gpu_run(w, w.total, "fp16", mode="fir")
     assert status == fe.FE_OK
-    # the oracle with the FP16-rounded scaled taps gives sum x * hs exactly
-    # (one nonzero term per output); scale back and round to FP16
-    hmax = float(np.max(np.abs(w.weights)))
-    sc = 14 - (np.frexp(hmax)[1] - 1)
-    hs = (w.weights * np.float32(2.0 ** sc)).astype(np.float16).astype(np.float64)
-    ref = oracle.channelize(w.raw, w.total, n, T, 128, hs, w.delays, w.phases, w.gains, want=("g",))
-    expect = (ref["g"] * 2.0 ** -sc).astype(np.float16).astype(np.float32)
+    if FIR_PATH["now"] == "matrix_fir":
+        # the oracle with the FP16-rounded scaled taps gives sum x * hs exactly
+        # (one nonzero term per output); scale back and round to FP16
+        hmax = float(np.max(np.abs(w.weights)))
+        sc = 14 - (np.frexp(hmax)[1] - 1)
+        hs = (w.weights * np.float32(2.0 ** sc)).astype(np.float16).astype(np.float64)
+        ref = oracle.channelize(w.raw, w.total, n, T, 128, hs, w.delays, w.phases, w.gains, want=("g",))
+        expect = (ref["g"] * 2.0 ** -sc).astype(np.float16).astype(np.float32)
+    else:
+        # the vector FIR: x * h rounded to float32 (one nonzero term per
+        # output), then to FP16 where it is stored
+        ref = oracle.channelize(w.raw, w.total, n, T, 128, w.weights, w.delays, w.phases, w.gains,
+                                want=("g",))
+        expect = ref["g"].astype(np.float32).astype(np.float16).astype(np.float32)
     assert np.array_equal(g, expect)
 
 
@@ -330,7 +353,7 @@ def spur_level_db(prec, n=1024, T=16, k0=192, amp=500.0, calls=16, N=1 << 23, se
     shape = synth.Shape(n=n, taps=T, antennas=1, samples=N, spectra_per_heap=256)
     w = synth.make_workload(shape, seed)
     M = N // (2 * n)
-    st = fe.Stream(n, T, 1, w.weights, N, spectra_per_heap=256, precision=prec)
+    st = fe.Stream(n, T, 1, w.weights, N, spectra_per_heap=256, precision=prec, path=FIR_PATH["now"])
     d = torch.zeros((1, 2, M), dtype=torch.float64, device="cuda")
     p = torch.zeros_like(d)
     g = np.zeros((1, 2, n, 2), dtype=np.float32)

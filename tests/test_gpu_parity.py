@@ -151,7 +151,10 @@ def test_hot_path_unpack_every_code_and_phase(prec):
     w.weights = np.ones_like(w.weights)
     F = np.arange(M * calls)
     w.delays[:] = ((F * 7 + 13 * np.arange(4).reshape(2, 2, 1)) % 121).astype(np.float64)
-    st = fe.Stream(n, 1, 2, w.weights, 2 * n * M, spectra_per_heap=S, precision=prec, path=PATH["now"])
+    # FP32 streams on the split and the fused kernels; FP16/BF16 streams on
+    # the vector FIR (under "split") and the matrix-core FIR (under "fused")
+    path = PATH["now"] if prec == "fp32" else {"split": "split", "fused": "matrix_fir"}[PATH["now"]]
+    st = fe.Stream(n, 1, 2, w.weights, 2 * n * M, spectra_per_heap=S, precision=prec, path=path)
     g, status = gpu_run(w, 2 * n * M, mode="fir", stream=st)
     st.close()
     assert status == fe.FE_OK
