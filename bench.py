@@ -70,6 +70,9 @@ def kernel_names(shape: synth.Shape, prec: str, path: str = "split"):
         tk = next(t for t in (4, 8, 16, 24, 32) if T <= t)
         if path == "fused":
             return {"fir": "pfb_fused_kernel<%d,%d>" % (n, tk), "turn": "corner_turn_kernel"}
+        if path == "split_folded":
+            # the FFT/post kernel writes the heaps itself (no corner-turn launch)
+            return {"fir": "fir_kernel<%d>" % tk, "post": "fft_post_heap_kernel<%d>" % n}
         return {"fir": "fir_kernel<%d>" % tk, "post": "fft_post_kernel<%d>" % n, "turn": "corner_turn_kernel"}
     tk = 16 if T <= 16 else 32
     fir = ("fir_mfma_kernel<%d,%s>" % (tk, prec) if path == "matrix_fir"
@@ -403,10 +406,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=None,
                     help="spectra per antenna for the CPU baseline (default: all)")
-    ap.add_argument("--variants", default="fp16,bf16,fp16_matrix_fir,fused,drift",
+    ap.add_argument("--variants", default="fp16,bf16,fp16_matrix_fir,fused,split_folded,drift",
                     help="variants timed beside the FP32 path: fp16, bf16 (DFT stages on the matrix "
                          "cores, vector FIR), fp16_matrix_fir, bf16_matrix_fir (FIR on the matrix cores "
-                         "too), split, fused (the FP32 stream on those kernel paths), drift (delays "
+                         "too), split, fused, split_folded (the FP32 stream on those kernel paths), drift (delays "
                          "drifting at 1e-5 samples/sample); comma list, empty for none")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-stream batch measurement")
     ap.add_argument("--no-service", action="store_true", help="skip the streaming-service measurement")
@@ -463,7 +466,7 @@ def main():
             variants[prec] = measure(fe, shape, w, sets, dev_arrays, prec[:4], args.steps, args.warmup,
                                      path="matrix_fir")
             continue
-        if prec in ("fused", "split"):
+        if prec in ("fused", "split", "split_folded"):
             # the same FP32 stream on another kernel path (fe_stream_set_schedule)
             variants["fp32_" + prec] = measure(fe, shape, w, sets, dev_arrays, "fp32", args.steps, args.warmup,
                                                path=prec)

@@ -230,7 +230,7 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
 fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches);
 
 /* Kernels of the path (fe_stream_set_schedule). */
-enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2, FE_PATH_MATRIX_FIR = 3 };
+enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2, FE_PATH_MATRIX_FIR = 3, FE_PATH_SPLIT_FOLDED = 4 };
 
 /* Choose the kernels that run a stream's calls, and the FIR schedule.
  * FE_PATH_SPLIT: a FIR kernel (steps 1-3a) writes the filtered samples as
@@ -246,6 +246,12 @@ enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2, FE_PATH_MATRIX_FI
  *   hi + lo).  Otherwise FP16/BF16 streams filter on the vector ALUs in
  *   float32 and store the filtered samples as FP16 (FP16 streams) or float32
  *   (BF16 streams) for the matrix-core DFT stages.
+ * FE_PATH_SPLIT_FOLDED (FP32 streams with n <= 8192; others run the split
+ *   path): the split path without the corner-turn kernel.  Each FFT/post
+ *   workgroup transforms both polarizations of one or two consecutive
+ *   spectra and writes every channel's bytes straight into the heap (Sec.
+ *   3.6 turns inside its post-processing kernel too): 2 bytes per sample
+ *   less device-memory traffic, one launch fewer.
  * FE_PATH_AUTO: fused for FP32 streams with T <= 8 and n <= 2048, else split
  *   (the fastest on MI355X for those shapes; for FP16/BF16 streams the
  *   vector FIR).
@@ -256,8 +262,8 @@ enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2, FE_PATH_MATRIX_FI
  * fir_batches outside 0..64. */
 fe_status fe_stream_set_schedule(fe_stream *s, int path, int fir_batches);
 
-/* The path the stream's calls run now (FE_PATH_SPLIT, FE_PATH_FUSED or
- * FE_PATH_MATRIX_FIR) and its fir_batches setting.  Either pointer may be
+/* The path the stream's calls run now (FE_PATH_SPLIT, FE_PATH_FUSED,
+ * FE_PATH_MATRIX_FIR or FE_PATH_SPLIT_FOLDED) and its fir_batches setting.  Either pointer may be
  * NULL. */
 fe_status fe_stream_get_schedule(const fe_stream *s, int *path, int *fir_batches);
 

@@ -619,7 +619,7 @@ __device__ __forceinline__ void fft_rest(float2 *buf, int tp, const float2 *tw_a
 // written instead.
 // ---------------------------------------------------------------------------
 
-enum { OUT_INT8 = 0, OUT_PREQUANT = 1 };
+enum { OUT_INT8 = 0, OUT_PREQUANT = 1, OUT_REG = 3 };   // OUT_REG: the int8 dwords stay in registers
 
 // Four values to four int8 in one dword (byte i = value i): saturate to
 // [-127, 127], round half to even.  Clamping first gives the same result as
@@ -676,7 +676,7 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
                                               const float2 *ph_lo, const float2 *__restrict__ untangle,
                                               const float2 *__restrict__ gn, bool ok, int64_t sp, int tid,
                                               uint32_t *__restrict__ spec8, float2 *__restrict__ y_out,
-                                              bool store = true)
+                                              bool store = true, uint32_t *qreg = nullptr)
 {
     // channel k = k0 + S i with k0 = 2 tid + e: the padded LDS offsets of k
     // and n - k, the coarse phase index and the table offsets all step by
@@ -725,6 +725,8 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
             Y[e] = ok ? cmul(gk, cmul(rot, X2)) : make_float2(0.f, 0.f);
         }
         if (!store) {
+        } else if (MODE == OUT_REG) {
+            qreg[i] = quant4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
         } else if (MODE == OUT_PREQUANT) {
             reinterpret_cast<float4 *>(y_out + sp * N)[j] = make_float4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
         } else {
@@ -798,6 +800,104 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
     __shared__ float2 ph_lo[64];
     fft_post_block<N, MODE>(xcd_logical(blockIdx.x, gridDim.x), true, threadIdx.x, buf, ph_hi, ph_lo, g,
                             delays, phases, gains, tw_all, untangle, spec8, y_out, status, M, D, mb, me);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2H: kernel 2 with the corner turn folded in (int8 output, n <= 8192).
+// One workgroup per (antenna, run of SPW consecutive spectra F0 ..): it
+// transforms and finishes the two polarizations of each spectrum in turn,
+// keeping each one's int8 pairs in registers, then writes every channel's
+// SPW spectra x 2 pols x (re, im) bytes straight to their place in the heap,
+// [A][M/S][n][S][2][2]: 4 SPW contiguous bytes per channel.  A wave's store
+// touches 64 lines, and consecutive runs of one antenna sit on one XCD, so
+// that XCD's L2 merges the runs' pieces of each line before they go to HBM.
+// SPW = 2 needs S even (a run never straddles heaps).
+// ---------------------------------------------------------------------------
+
+template <int N, int SPW>
+__global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_heap_kernel(
+    const float *__restrict__ g, const double *__restrict__ delays,
+    const double *__restrict__ phases, const float2 *__restrict__ gains,
+    const float2 *__restrict__ tw_all, const float2 *__restrict__ untangle,
+    int8_t *__restrict__ out, int *__restrict__ status, int M, int D, int S)
+{
+    constexpr int NT = N / 16;             // threads, 16 points each
+    constexpr int NH = N / 64;
+    constexpr int P = N / 2 / NT;          // channel pairs per thread
+    __shared__ float2 buf[lds_len<N>()];
+    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[64];
+    const int runs = M / SPW;
+    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    const int a = item / runs;
+    const int F0 = (item % runs) * SPW;
+
+    // q[2 f + p]: the int8 dwords of spectrum F0 + f, pol p.  The loop is
+    // not unrolled (unrolled, the compiler hoists every transform's loads to
+    // the top and spills); each pass shifts its result in at the end.
+    constexpr int Q = 2 * SPW;
+    uint32_t q[Q][P];
+#pragma unroll 1
+    for (int fp = 0; fp < Q; ++fp) {
+        const int f = fp >> 1, p = fp & 1;
+        // a fresh copy of the thread index and table bases per pass, so that
+        // the addresses and table loads derived from them are not hoisted
+        // out of the loop (and held across it, in registers it does not have)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const float2 *tw = tw_all, *ut = untangle;
+        asm volatile("" : "+s"(tw), "+s"(ut));
+        const int64_t sp = (int64_t(a) * 2 + p) * M + F0 + f;
+        const float2 *src = reinterpret_cast<const float2 *>(g) + sp * N;
+        float2 v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = load_nt(src + tid + r * NT);
+        int c;
+        double tau;
+        const bool ok = split_delay(delays[sp], D, c, tau);
+        if (!ok && tid == 0)
+            atomicOr(status, 1);
+        if (fp > 0)
+            __syncthreads();               // the previous pass's readers are done with LDS
+        phase_tables<N, NT>(ph_hi, ph_lo, phases[sp], tau, 0.5f, tid);
+        Dft<16>::run(v);
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            buf[lds_pad(tid * 16 + r)] = v[r];
+        __syncthreads();
+        fft_rest<N, 1>(buf, tid, tw);
+        uint32_t qn[P];
+        post_spectrum<N, NT, OUT_REG>(buf, ph_hi, ph_lo, ut, gains + (int64_t(a) * 2 + p) * N, ok, sp,
+                                      tid, nullptr, nullptr, true, qn);
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+#pragma unroll
+            for (int u = 0; u + 1 < Q; ++u)
+                q[u][i] = q[u + 1][i];
+            q[Q - 1][i] = qn[i];
+        }
+    }
+
+    // channel k's dword for one spectrum: (re, im) of pol 0, then of pol 1
+    uint32_t *o = reinterpret_cast<uint32_t *>(out) + (int64_t(a) * (M / S) + F0 / S) * N * S + F0 % S;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int j = int(threadIdx.x) + NT * i;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const uint32_t sel = e == 0 ? 0x05040100u : 0x07060302u;
+            uint32_t w[SPW];
+#pragma unroll
+            for (int f = 0; f < SPW; ++f)
+                w[f] = __builtin_amdgcn_perm(q[2 * f + 1][i], q[2 * f][i], sel);
+            uint32_t *dst = o + int64_t(2 * j + e) * S;
+            if constexpr (SPW == 2)
+                *reinterpret_cast<uint2 *>(dst) = make_uint2(w[0], w[1]);
+            else
+                *dst = w[0];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2588,6 +2688,39 @@ void launch_post_N(const fe_stream *s, const Work &wk, int M, const double *dela
                            M, s->D, mb, me);
 }
 
+// Kernel 2H in place of kernels 2 and 3 (FP32, n <= 8192, int8 output)
+template <int N>
+void launch_post_heap_N(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
+                        const float *gains, int8_t *out)
+{
+    if (s->S % 2 == 0)
+        hipLaunchKernelGGL((fft_post_heap_kernel<N, 2>), dim3(unsigned(s->A * (M / 2))), dim3(N / 16), 0,
+                           s->stream, wk.g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, out, s->d_status, M, s->D, s->S);
+    else
+        hipLaunchKernelGGL((fft_post_heap_kernel<N, 1>), dim3(unsigned(s->A * M)), dim3(N / 16), 0,
+                           s->stream, wk.g, delays, phases, reinterpret_cast<const float2 *>(gains), s->d_tw,
+                           s->d_untangle, out, s->d_status, M, s->D, s->S);
+}
+
+bool heap_fold(const fe_stream *s)
+{
+    return s->prec == FE_PREC_FP32 && s->n <= 8192 && s->path == FE_PATH_SPLIT_FOLDED;
+}
+
+void launch_post_heap(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
+                      const float *gains, int8_t *out)
+{
+    switch (s->n) {
+    case 256: launch_post_heap_N<256>(s, wk, M, delays, phases, gains, out); break;
+    case 512: launch_post_heap_N<512>(s, wk, M, delays, phases, gains, out); break;
+    case 1024: launch_post_heap_N<1024>(s, wk, M, delays, phases, gains, out); break;
+    case 2048: launch_post_heap_N<2048>(s, wk, M, delays, phases, gains, out); break;
+    case 4096: launch_post_heap_N<4096>(s, wk, M, delays, phases, gains, out); break;
+    case 8192: launch_post_heap_N<8192>(s, wk, M, delays, phases, gains, out); break;
+    }
+}
+
 template <int N, int PREC>
 void launch_post_mfma_N(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
                         const float *gains, float *y_out, int mb, int me)
@@ -2869,10 +3002,14 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
     mark(1);
     launch_history_update(s, wk, raw, N);
     mark(2);
-    if (!g_out && !fused)
+    // int8 output on the FP32 split path: the FFT/post kernel writes the heaps
+    const bool heap = !g_out && !y_out && !fused && heap_fold(s);
+    if (heap)
+        launch_post_heap(s, wk, M, delays, phases, gains, out);
+    else if (!g_out && !fused)
         launch_post(s, wk, M, delays, phases, gains, y_out, 0, M);
     mark(3);
-    if (!g_out && !y_out)
+    if (!g_out && !y_out && !heap)
         launch_corner_turn(s, wk, M, out);
     mark(4);
     st = hip_status(hipGetLastError());
@@ -3226,8 +3363,14 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
     const int ncand = 5;
     // (the FIR engine of FP16/BF16 streams is left as set: the two engines
     // round differently, and tuning keeps results bit for bit)
-    const int paths[2] = {FE_PATH_SPLIT, FE_PATH_FUSED};
-    const int npaths = fused_eligible(s) ? 2 : 1;
+    int paths[3], npaths = 0;
+    if (s->prec == FE_PREC_FP32) {
+        paths[npaths++] = FE_PATH_SPLIT;
+        if (s->n <= 8192)
+            paths[npaths++] = FE_PATH_SPLIT_FOLDED;
+        if (fused_eligible(s))
+            paths[npaths++] = FE_PATH_FUSED;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0)
@@ -3240,8 +3383,8 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
     float best_ms = 3.0e38f;
     int best = 0, best_path = saved_path;
     st = FE_OK;
-    for (int c = 0; c < ncand * npaths && st == FE_OK; ++c) {
-        s->path = npaths > 1 ? paths[c / ncand] : saved_path;
+    for (int c = 0; c < ncand * std::max(npaths, 1) && st == FE_OK; ++c) {
+        s->path = npaths > 0 ? paths[c / ncand] : saved_path;
         s->fir_batches = cand[c % ncand];
         st = channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr);   // warm
         if (st != FE_OK)
@@ -3287,7 +3430,7 @@ fe_status fe_stream_set_schedule(fe_stream *s, int path, int fir_batches)
 {
     if (!s || fir_batches < 0 || fir_batches > 64
         || (path != FE_PATH_AUTO && path != FE_PATH_SPLIT && path != FE_PATH_FUSED
-            && path != FE_PATH_MATRIX_FIR))
+            && path != FE_PATH_MATRIX_FIR && path != FE_PATH_SPLIT_FOLDED))
         return FE_EINVAL;
     s->path = path;
     s->fir_batches = fir_batches;
@@ -3299,7 +3442,8 @@ fe_status fe_stream_get_schedule(const fe_stream *s, int *path, int *fir_batches
     if (!s)
         return FE_EINVAL;
     if (path)
-        *path = fused_path(s) ? FE_PATH_FUSED : matrix_fir(s) ? FE_PATH_MATRIX_FIR : FE_PATH_SPLIT;
+        *path = fused_path(s) ? FE_PATH_FUSED : matrix_fir(s) ? FE_PATH_MATRIX_FIR
+                : heap_fold(s) ? FE_PATH_SPLIT_FOLDED : FE_PATH_SPLIT;
     if (fir_batches)
         *fir_batches = s->fir_batches;
     return FE_OK;

@@ -18,8 +18,9 @@ FE_OK, FE_EINVAL, FE_ENOMEM, FE_EHIP, FE_EDELAY, FE_ESIZE = 0, -1, -2, -3, -4, -
 FE_NOALLOC_SCRATCH_BYTES = 64 << 20         # include/fengine.h
 FE_PREC_FP32, FE_PREC_FP16, FE_PREC_BF16 = 0, 1, 2
 PRECISIONS = {"fp32": FE_PREC_FP32, "fp16": FE_PREC_FP16, "bf16": FE_PREC_BF16}
-FE_PATH_AUTO, FE_PATH_SPLIT, FE_PATH_FUSED, FE_PATH_MATRIX_FIR = 0, 1, 2, 3
-PATHS = {"auto": FE_PATH_AUTO, "split": FE_PATH_SPLIT, "fused": FE_PATH_FUSED, "matrix_fir": FE_PATH_MATRIX_FIR}
+FE_PATH_AUTO, FE_PATH_SPLIT, FE_PATH_FUSED, FE_PATH_MATRIX_FIR, FE_PATH_SPLIT_FOLDED = 0, 1, 2, 3, 4
+PATHS = {"auto": FE_PATH_AUTO, "split": FE_PATH_SPLIT, "fused": FE_PATH_FUSED, "matrix_fir": FE_PATH_MATRIX_FIR,
+         "split_folded": FE_PATH_SPLIT_FOLDED}
 
 
 class FEngineError(RuntimeError):
@@ -312,7 +313,7 @@ class Stream:
         p, b = ctypes.c_int(), ctypes.c_int()
         _check(load_library().fe_stream_get_schedule(self._h, ctypes.byref(p), ctypes.byref(b)),
                "fe_stream_get_schedule")
-        names = {FE_PATH_FUSED: "fused", FE_PATH_MATRIX_FIR: "matrix_fir"}
+        names = {FE_PATH_FUSED: "fused", FE_PATH_MATRIX_FIR: "matrix_fir", FE_PATH_SPLIT_FOLDED: "split_folded"}
         return names.get(p.value, "split"), int(b.value)
 
     def _call(self, raw, n_samples, delays, phases, gains, out) -> _Call:

@@ -32,14 +32,15 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-# Every stream test runs on both kernel paths (fe_stream_set_schedule): the
-# split path (FIR kernel, filtered samples in device memory, FFT/post kernel)
-# and the fused kernel (FP32, n <= 4096, T <= 16; other shapes run split
-# either way).
+# Every stream test runs on each kernel path (fe_stream_set_schedule): the
+# split path (FIR kernel, filtered samples in device memory, FFT/post kernel,
+# corner turn), the fused kernel (FP32, n <= 4096, T <= 16) and the split
+# path whose FFT/post kernel writes the heaps itself (FP32, n <= 8192);
+# shapes a path cannot run run split either way.
 PATH = {"now": "split"}
 
 
-@pytest.fixture(autouse=True, params=["split", "fused"])
+@pytest.fixture(autouse=True, params=["split", "fused", "split_folded"])
 def kernel_path(request):
     PATH["now"] = request.param
     _say("[path %s]" % request.param)
@@ -153,7 +154,7 @@ def test_hot_path_unpack_every_code_and_phase(prec):
     w.delays[:] = ((F * 7 + 13 * np.arange(4).reshape(2, 2, 1)) % 121).astype(np.float64)
     # FP32 streams on the split and the fused kernels; FP16/BF16 streams on
     # the vector FIR (under "split") and the matrix-core FIR (under "fused")
-    path = PATH["now"] if prec == "fp32" else {"split": "split", "fused": "matrix_fir"}[PATH["now"]]
+    path = PATH["now"] if prec == "fp32" else {"fused": "matrix_fir"}.get(PATH["now"], "split")
     st = fe.Stream(n, 1, 2, w.weights, 2 * n * M, spectra_per_heap=S, precision=prec, path=path)
     g, status = gpu_run(w, 2 * n * M, mode="fir", stream=st)
     st.close()
@@ -284,7 +285,12 @@ def test_prequant_matches_oracle(n, T, A, S, M, calls):
     _say("  Y normwise %.3g elementwise %.3g" % (nw, el))
 
 
-@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10] + CASES[13:15])
+# odd heap sizes: heaps of 3 and 1 spectra (the FFT/post kernel then writes
+# one spectrum's bytes per channel at a time)
+ODD_HEAPS = [(1024, 16, 2, 3, 33, 2), (8192, 8, 1, 1, 7, 1)]
+
+
+@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10] + CASES[13:15] + ODD_HEAPS)
 def test_int8_matches_oracle(n, T, A, S, M, calls):
     _say("int8 n=%d T=%d A=%d S=%d M=%d calls=%d" % (n, T, A, S, M, calls))
     shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
