@@ -124,21 +124,30 @@ __device__ __forceinline__ int xcd_logical(int b, int G)
 // ---------------------------------------------------------------------------
 // Kernel 1: unpack + coarse delay + FIR (Eq. (1)).
 //
-// Thread = one column t of one stream (antenna, pol) for a run of R
-// consecutive spectra.  g_{F,t} = sum_j s[2n(F-T+1) - c_F + t + 2nj] h[t+2nj].
-// Viewed down column t, spectrum F reads rows F-T+1 .. F of the 2n-wide
+// Thread = two adjacent columns t, t+1 (t even) of one stream (antenna, pol)
+// for a run of R consecutive spectra.
+//   g_{F,t} = sum_j s[2n(F-T+1) - c_F + t + 2nj] h[t+2nj].
+// Viewed down a column, spectrum F reads rows F-T+1 .. F of the 2n-wide
 // sample matrix shifted by c_F, so consecutive spectra with equal c share
-// T-1 rows and each new spectrum needs one new sample.  Spectra go in groups
-// of T: the group's T new samples are loaded together (memory-level
-// parallelism), one group ahead of their use, and its T outputs are formed
-// from a 2T-1 register window.  The workgroup first splits the delays of up
-// to FIR_SEG spectra into an LDS table (one per thread).  Each wave then
-// walks the spectra in spans of one delay (found with one table read per
-// lane and a ballot): a span's groups start at its first spectrum and its
-// last group is padded (the padding outputs are not stored), so a delay
-// step costs one refill of the T-1 older rows and part of one group.
-// Spectra with an invalid delay or rows before the call (the history seam)
-// take a general per-spectrum path.
+// T-1 rows and each new spectrum needs one new row.  A row's two samples of
+// the pair, i = 2n r - c + t and i + 1 (20 bits), lie in the 4 bytes from
+// byte floor(5 i / 4): one unaligned dword load brings both, a byte swap and
+// two sign-extending bitfield extracts unpack them, and the two outputs
+// leave in one 8-byte (FP16: 4-byte) store.  (With one column per thread the
+// kernel issues twice the vector memory instructions, and their address
+// processing, not HBM, bounds it.)  Spectra go in groups of G = T (T < 8), 8
+// (T <= 16) or 4: a group's G new rows are loaded together (memory-level
+// parallelism), one group ahead of their use, and its G outputs per column
+// come from a (T-1+G)-row register window.  The workgroup first splits the
+// delays of up to FIR_SEG spectra into an LDS table (one per thread).  Each
+// wave then walks the spectra in spans of one delay (found with one table
+// read per lane and a ballot): a span's groups start at its first spectrum
+// and its last group is padded (the padding outputs are not stored), so a
+// delay step costs one refill of the T-1 older rows and part of one group.
+// Spectra with an invalid delay or rows before the region take a general
+// per-spectrum path.  The region's last row is read from one byte earlier by
+// the one lane whose pair ends the region (its dword would pass the end by
+// a byte), and the word is shifted back.
 // ---------------------------------------------------------------------------
 
 constexpr int FIR_THREADS = 256;
@@ -146,20 +155,11 @@ constexpr int FIR_SEG = 1024;              // spectra per delay table
 
 // Raw buffer descriptor (gfx9 family): base, no stride, `bytes` records;
 // loads outside [0, bytes) return zero, stores outside are dropped.  Used for
-// aligned 32-bit stores only (16-bit buffer loads at odd byte addresses do
-// not behave like unaligned global loads).
+// aligned stores only (buffer loads at unaligned byte addresses do not
+// behave like unaligned global loads).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, int(bytes), 0x00020000);
-}
-
-// Store one float through a buffer descriptor (the builtin's payload is a
-// 32-bit integer: pass the bits, not a converted value).
-__device__ __forceinline__ void store_f32(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    // cache policy 2 = non-temporal: the filtered samples stream to memory
-    // without displacing the taps and input rows from L2
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 2);
 }
 
 // How the FIR stores its filtered samples g: float32 (FP32 and BF16 streams),
@@ -167,46 +167,42 @@ __device__ __forceinline__ void store_f32(float v, __amdgpu_buffer_rsrc_t r, uin
 // FP16-rounded value (FP16 streams' FIR-stage debug output).
 enum { G_F32 = 0, G_F16 = 1, G_F32_AS_F16 = 2 };
 
-template <int GM>
-__device__ __forceinline__ void store_g(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
-{
-    if constexpr (GM == G_F16) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)v), r, voff, soff, 2);
-    } else {
-        if constexpr (GM == G_F32_AS_F16)
-            v = float((_Float16)v);
-        store_f32(v, r, voff, soff);
-    }
-}
-
-// Unaligned 16-bit global load (little-endian) at byte `off` of a
+// Unaligned 32-bit global load (little-endian) at byte `off` of a
 // wave-uniform base in the global address space (so the address is an SGPR
 // pair plus one 32-bit VGPR).
 typedef const uint8_t __attribute__((address_space(1))) *gptr8;
-typedef uint16_t __attribute__((aligned(1))) u16_unaligned;
-__device__ __forceinline__ uint32_t load_u16(gptr8 base, uint32_t off)
+typedef uint32_t __attribute__((aligned(1))) u32_unaligned;
+__device__ __forceinline__ uint32_t load_u32u(gptr8 base, uint32_t off)
 {
-    return *reinterpret_cast<const u16_unaligned __attribute__((address_space(1))) *>(base + off);
+    return *reinterpret_cast<const u32_unaligned __attribute__((address_space(1))) *>(base + off);
 }
 
-// 10-bit sample from a little-endian 16-bit load u of the bytes holding it;
-// its MSB sits `lo_shift` + 9 bits up in the big-endian (byte-swapped) word.
-__device__ __forceinline__ float field10(uint32_t u, uint32_t lo_shift)
+// Store two filtered samples (columns t, t+1) through a buffer descriptor,
+// non-temporally (cache policy 2: they stream to memory without displacing
+// the taps and input rows from L2); the builtins' payloads are integers, so
+// the bits are passed, not converted values.
+typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
+
+// workgroups per CU the register budget allows (two columns' windows)
+#define FIR_WG_PER_CU(T) ((T) <= 8 ? 4 : (T) <= 16 ? 3 : 2)
+
+template <int GM>
+__device__ __forceinline__ void store_g2(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, u, 0x0C0C0001u));   // byte swap
-    // sign-extending extract; the builtin's result type is unsigned, so cast
-    // back to int before converting (else the conversion is unsigned)
-    const int32_t x = int32_t(__builtin_amdgcn_sbfe(be, lo_shift, 10u));
-    return float(x);
+    if constexpr (GM == G_F16) {
+        const uint32_t w = uint32_t(__builtin_bit_cast(uint16_t, (_Float16)a))
+                           | (uint32_t(__builtin_bit_cast(uint16_t, (_Float16)b)) << 16);
+        __builtin_amdgcn_raw_buffer_store_b32(w, r, voff, soff, 2);
+    } else {
+        if constexpr (GM == G_F32_AS_F16) {
+            a = float((_Float16)a);
+            b = float((_Float16)b);
+        }
+        const v2u32 v = {__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)};
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 2);
+    }
 }
 
-// The body of kernel 1 for logical block lb (tile: stream, run, column
-// block); s_c is an LDS table of FIR_SEG ints.
-// Rows come from `raw` (mrows rows of 2n samples per stream, row 0 at the
-// start of raw); spectrum m of that row numbering is spectrum m - moff of the
-// call (its delay and its filtered samples).  The call's own chunk has
-// moff = 0, mrows = M; a staged seam (the history's tail and the chunk's first
-// rows, one buffer per stream) has moff = its rows before the chunk.
 template <int T, int GM = G_F32>
 __device__ __forceinline__ void fir_block(
     int lb, int *__restrict__ s_c,
@@ -216,89 +212,75 @@ __device__ __forceinline__ void fir_block(
     void *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
     int moff, int mrows)
 {
+    constexpr int G = T < 8 ? T : (T <= 16 ? 8 : 4);         // spectra per group
     constexpr uint32_t ES = GM == G_F16 ? 2u : 4u;          // bytes per stored sample
     const int cb = lb % colblocks;
     const int rest = lb / colblocks;
     const int run = rest % runs;
     const int s = rest / runs;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int t_blk = cb * FIR_THREADS;
-    const int t = t_blk + tid;
-    const int m0 = mb + run * R;            // this launch covers spectra [mb, me)
+    const int t_blk = cb * 2 * FIR_THREADS;                   // the block's first column
+    const int t = t_blk + 2 * tid;                            // the pair's first column
+    const int m0 = mb + run * R;
     const int mend = min(m0 + R, me);
 
-    float h[T];
+    float2 h[T];
 #pragma unroll
     for (int j = 0; j < T; ++j)
-        h[j] = taps[t + n2 * j];
+        h[j] = *reinterpret_cast<const float2 *>(taps + t + n2 * j);
 
     const double *ds = delays + int64_t(s) * M;
     const uint8_t *rs = raw + int64_t(s) * raw_stride;
     const uint8_t *hs = hist + int64_t(s) * hist_stride;
     uint8_t *gs = static_cast<uint8_t *>(g) + int64_t(s) * M * n2 * ES;
     const __amdgpu_buffer_rsrc_t rg = make_rsrc(gs, uint32_t(int64_t(M) * n2 * ES));
-    const int row_bytes = (n2 / 4) * 5;                       // 2n samples of 10 bits
+    const int row_bytes = (n2 / 4) * 5;
+    const uint32_t region_bytes = uint32_t(mrows) * uint32_t(row_bytes);
     const uint32_t t_bytes = uint32_t(t) * ES;
 
-    // X: rows g0-T+1 .. g0-1 of column t at delay c_cur (raw 16-bit words
-    // straight after a refill); N: the raw words of rows g0 .. g0+T-1,
-    // loaded one group ahead of their use
-    float X[T - 1];
+    // X0, X1: rows g0-T+1 .. g0-1 of the two columns at delay c_cur; W: the
+    // raw words of rows g0 .. g0+G-1, loaded one group ahead of their use
+    float X0[T - 1], X1[T - 1];
 #pragma unroll
     for (int i = 0; i < T - 1; ++i)
-        X[i] = 0.f;
+        X0[i] = X1[i] = 0.f;
     int c_cur = -1;
-    uint32_t N[T];
+    uint32_t W[G];
+    uint32_t tail = 0;                                        // 1: this lane's last-row word is read a byte early
     auto issue = [&](int g0, int c, bool refill) {
-        // rows g0 .. g0+T-1 at delay c (rows past the call's last one, which
-        // only padded outputs use, read that last row): byte (5 i0)/4 of row
-        // pointers rs + r*row_bytes.  One running row pointer, kept a scalar
-        // operand by the empty asm: folded into the lane offset it would cost
-        // two VGPRs and two adds per row.
         const uint32_t voff = uint32_t(5 * (n2 * g0 - c + t)) >> 2;
         if (refill) {
-            const uint32_t v0 = voff - uint32_t((T - 1) * row_bytes);      // row g0-T+1, in the call
+            const uint32_t v0 = voff - uint32_t((T - 1) * row_bytes);      // row g0-T+1, in the region
             gptr8 rp = (gptr8)rs;
 #pragma unroll
             for (int k = 0; k < T - 1; ++k) {
                 asm volatile("" : "+s"(rp));
-                X[k] = __builtin_bit_cast(float, load_u16(rp, v0));
+                X0[k] = __builtin_bit_cast(float, load_u32u(rp, v0));
                 rp += row_bytes;
             }
         }
         gptr8 rp = (gptr8)rs;
 #pragma unroll
-        for (int r = 0; r < T; ++r) {
+        for (int r = 0; r < G; ++r) {
             asm volatile("" : "+s"(rp));
-            N[r] = load_u16(rp, voff);
+            // rows past the region's last one (only padded outputs use them)
+            // read that last row
+            W[r] = load_u32u(rp, g0 + r >= mrows - 1 ? voff - tail : voff);
             if (g0 + r + 1 < mrows)
                 rp += row_bytes;
         }
     };
 
-    // outputs of the last group, stored right after the next loads are
-    // issued (loads and stores share one in-order wait counter; the stores
-    // are unconditional so that the compiler's wait counts stay the same on
-    // every path).  Outputs r >= pend_cnt are padding: their scalar offset
-    // DROP puts them beyond the buffer's record count and the hardware drops
-    // them.
+    // a group's outputs are stored as soon as they are formed, behind the
+    // next group's loads (one in-order counter covers both, so the wait for
+    // those loads counts exactly G later stores: the stores are
+    // unconditional, and outputs r >= the group's count take the scalar
+    // offset DROP, beyond the buffer's record count, where the hardware
+    // drops them)
     constexpr uint32_t DROP = 0x80000000u;
-    float pend[T];
-#pragma unroll
-    for (int r = 0; r < T; ++r)
-        pend[r] = 0.f;
-    int pend_cnt = 0;
-    uint32_t pend_soff = 0;
-    auto flush = [&]() {
-#pragma unroll
-        for (int r = 0; r < T; ++r)
-            store_g<GM>(pend[r], rg, t_bytes, r < pend_cnt ? pend_soff + uint32_t(r * n2) * ES : DROP);
-        pend_cnt = 0;
-    };
 
     for (int sa = m0; sa < mend; sa += FIR_SEG) {
         const int se = min(sa + FIR_SEG, mend);
-        // delay split of the segment's spectra, one per thread
         __syncthreads();                                      // the last segment's table is read
         for (int i = tid; i < se - sa; i += FIR_THREADS) {
             int c;
@@ -311,27 +293,21 @@ __device__ __forceinline__ void fir_block(
         while (m < se) {
             const int c = __builtin_amdgcn_readfirstlane(s_c[m - sa]);
             if (c < 0 || int64_t(n2) * (m - T + 1) - c + t_blk < 0) {
-                // general path for spectrum m (an invalid delay, or rows
-                // before the call): all T rows loaded, invalid delays read at
-                // delay 0 and output zeros
-                flush();
-                int i = n2 * (m - T + 1) - max(c, 0) + t;      // sample of row m-T+1
-                float acc = 0.f;
+                // general path for spectrum m, both columns
+                int i = n2 * (m - T + 1) - max(c, 0) + t;
+                float a0 = 0.f, a1 = 0.f;
 #pragma unroll
                 for (int j = 0; j < T; ++j) {
-                    // (a lane value stepped row by row: hoisted, the T row
-                    // offsets would each hold scalar registers)
                     asm volatile("" : "+v"(i));
-                    acc = fmaf(float(sample_at(rs, hs, i, H)), h[j], acc);
+                    a0 = fmaf(float(sample_at(rs, hs, i, H)), h[j].x, a0);
+                    a1 = fmaf(float(sample_at(rs, hs, i + 1, H)), h[j].y, a1);
                     i += n2;
                 }
-                store_g<GM>(c >= 0 ? acc : 0.f, rg, t_bytes, uint32_t((m - moff) * n2) * ES);
-                c_cur = -1;                                   // X holds no rows
+                store_g2<GM>(c >= 0 ? a0 : 0.f, c >= 0 ? a1 : 0.f, rg, t_bytes, uint32_t((m - moff) * n2) * ES);
+                c_cur = -1;
                 ++m;
                 continue;
             }
-            // span of spectra from m with this delay: 64 table entries at a
-            // time, one per lane
             int send = m;
             for (;;) {
                 const int ix = send - sa + lane;
@@ -343,70 +319,72 @@ __device__ __forceinline__ void fir_block(
                 }
                 send += 64;
             }
-            // its groups g0 = m, m+T, ..., the last one padded: the first
-            // group's rows (and, unless they continue the held window, its
-            // T-1 older rows), then each group's new rows one group ahead
+            // the lane whose pair ends the region at this delay reads its
+            // last-row word one byte early
+            tail = (uint32_t(5 * (n2 * (mrows - 1) - c + t)) >> 2) + 4u > region_bytes ? 1u : 0u;
             const bool refill = c != c_cur;
             issue(m, c, refill);
-            flush();
-            const uint32_t lo = 6u - ((uint32_t(t - c) & 3u) << 1);    // bit phase of every sample
+            const uint32_t lo = 22u - ((uint32_t(t - c) & 3u) << 1);   // first sample's field in the swapped word
             if (refill) {
 #pragma unroll
-                for (int i = 0; i < T - 1; ++i)
-                    X[i] = field10(__builtin_bit_cast(uint32_t, X[i]), lo);
-            }
-            for (int g0 = m;; g0 += T) {
-                float Y[T];
-#pragma unroll
-                for (int r = 0; r < T; ++r)
-                    Y[r] = field10(N[r], lo);
-                const bool ahead = g0 + T < send;
-                // unconditional, so that the loaded registers are the same on
-                // every path (a conditional load makes the compiler copy them,
-                // waiting for the loads); after the span's last group its rows
-                // are read again and not used
-                issue(ahead ? g0 + T : g0, c, false);
-                // the last group's stores go behind the loads, on every path T
-                // of them: the wait for the loads then counts exactly T later
-                // operations
-                flush();
-                __builtin_amdgcn_sched_barrier(0);            // keep the memory operations ahead of the arithmetic
-#pragma unroll
-                for (int r = 0; r < T; ++r) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int j = 0; j < T; ++j)
-                        acc = fmaf(j + r < T - 1 ? X[j + r] : Y[j + r - (T - 1)], h[j], acc);
-                    pend[r] = acc;
+                for (int i = 0; i < T - 1; ++i) {
+                    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, __builtin_bit_cast(uint32_t, X0[i]), 0x00010203u));
+                    X0[i] = float(int32_t(__builtin_amdgcn_sbfe(be, lo, 10u)));
+                    X1[i] = float(int32_t(__builtin_amdgcn_sbfe(be, lo - 10u, 10u)));
                 }
-                pend_cnt = min(T, send - g0);
-                pend_soff = uint32_t((g0 - moff) * n2) * ES;
-                // rows g0+1 .. g0+T-1 become the older rows of the next group
+            }
+            for (int g0 = m;; g0 += G) {
+                float Y0[G], Y1[G];
 #pragma unroll
-                for (int i = 0; i < T - 1; ++i)
-                    X[i] = Y[i + 1];
+                for (int r = 0; r < G; ++r) {
+                    uint32_t w = W[r];
+                    if (g0 + r >= mrows - 1)
+                        w >>= 8u * tail;
+                    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, w, 0x00010203u));
+                    Y0[r] = float(int32_t(__builtin_amdgcn_sbfe(be, lo, 10u)));
+                    Y1[r] = float(int32_t(__builtin_amdgcn_sbfe(be, lo - 10u, 10u)));
+                }
+                const bool ahead = g0 + G < send;
+                issue(ahead ? g0 + G : g0, c, false);
+                __builtin_amdgcn_sched_barrier(0);            // keep the loads ahead of the arithmetic
+                const int cnt = min(G, send - g0);
+                const uint32_t soff = uint32_t((g0 - moff) * n2) * ES;
+#pragma unroll
+                for (int r = 0; r < G; ++r) {
+                    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+                    for (int j = 0; j < T; ++j) {
+                        a0 = fmaf(j + r < T - 1 ? X0[j + r] : Y0[j + r - (T - 1)], h[j].x, a0);
+                        a1 = fmaf(j + r < T - 1 ? X1[j + r] : Y1[j + r - (T - 1)], h[j].y, a1);
+                    }
+                    store_g2<GM>(a0, a1, rg, t_bytes, r < cnt ? soff + uint32_t(r * n2) * ES : DROP);
+                }
+                // the window's last T-1 rows become the older rows of the next group
+#pragma unroll
+                for (int i = 0; i < T - 1; ++i) {
+                    X0[i] = i + G < T - 1 ? X0[i + G] : Y0[i + G - (T - 1)];
+                    X1[i] = i + G < T - 1 ? X1[i + G] : Y1[i + G - (T - 1)];
+                }
                 if (!ahead)
                     break;
             }
-            // a padded last group leaves rows past the span in X
-            c_cur = (send - m) % T == 0 ? c : -1;
+            c_cur = (send - m) % G == 0 ? c : -1;
             m = send;
         }
     }
-    flush();
 }
 
 template <int T, int GM>
-__global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_kernel(
+__global__ __launch_bounds__(FIR_THREADS, FIR_WG_PER_CU(T)) void fir_kernel(
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
     void *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
     int moff, int mrows)
 {
-    __shared__ int s_c[FIR_SEG];            // coarse delay of each spectrum of the segment, -1 if invalid
+    __shared__ int s_c[FIR_SEG];
     fir_block<T, GM>(xcd_logical(blockIdx.x, gridDim.x), s_c, raw, raw_stride, hist, hist_stride, H, taps,
-                     delays, g, n2, M, D, R, colblocks, runs, mb, me, moff, mrows);
+                      delays, g, n2, M, D, R, colblocks, runs, mb, me, moff, mrows);
 }
 
 // The seam of a call for the FIR: per stream, dst = [zero bytes | the
@@ -926,13 +904,6 @@ constexpr int PF_S = 4;                     // spectra per step
 
 enum { OUT_G = 2 };                         // (besides OUT_INT8, OUT_PREQUANT) the FIR output g
 
-typedef uint32_t __attribute__((aligned(1))) u32_unaligned;
-
-// unaligned 32-bit global load at byte `off` of a wave-uniform base
-__device__ __forceinline__ uint32_t load_u32u(gptr8 base, uint32_t off)
-{
-    return *reinterpret_cast<const u32_unaligned __attribute__((address_space(1))) *>(base + off);
-}
 
 // Radix-16 Stockham pass with L = 1 (no twiddles) over one polarization's n
 // points in LDS: butterfly b reads z[b + q n/16], writes 16 b + r.
@@ -2208,7 +2179,7 @@ __device__ __forceinline__ int find_job(const J *__restrict__ jobs, int njobs, i
 }
 
 template <int T>
-__global__ __launch_bounds__(FIR_THREADS, (T <= 16 ? 4 : 2)) void fir_jobs_kernel(const FirJob *__restrict__ jobs,
+__global__ __launch_bounds__(FIR_THREADS, FIR_WG_PER_CU(T)) void fir_jobs_kernel(const FirJob *__restrict__ jobs,
                                                                                   int njobs)
 {
     __shared__ int s_c[FIR_SEG];
@@ -2555,7 +2526,7 @@ void launch_fir_range(const fe_stream *s, const uint8_t *raw, int64_t raw_stride
 {
     const int n2 = 2 * s->n;
     const int streams = 2 * s->A;
-    const int colblocks = n2 / FIR_THREADS;
+    const int colblocks = n2 / (2 * FIR_THREADS);            // a column pair per thread
     // runs of R spectra (whole batches of B = (64/T)T); longer runs load the
     // taps less often, shorter ones give more workgroups
     constexpr int B = (64 / T) * T;
@@ -3545,7 +3516,7 @@ void plan_add(BatchPlan &P, std::vector<BatchPlan::Launch> &list, int kind, int 
 // FIR run length over `spectra` spectra (as launch_fir_range)
 int fir_run_length(const fe_stream *s, int T, int spectra)
 {
-    const int streams = 2 * s->A, colblocks = 2 * s->n / FIR_THREADS, B = (64 / T) * T;
+    const int streams = 2 * s->A, colblocks = 2 * s->n / (2 * FIR_THREADS), B = (64 / T) * T;
     if (s->fir_batches > 0)
         return s->fir_batches * B;
     int R = 4 * B;
@@ -3585,7 +3556,7 @@ void build_plan(const fe_batch *b, const fe_call *calls, BatchPlan &P)
         F.n2 = n2;
         F.M = M;
         F.D = s->D;
-        F.colblocks = n2 / FIR_THREADS;
+        F.colblocks = n2 / (2 * FIR_THREADS);
         // the seam from a staging buffer, the rest from the chunk
         const int S0 = std::min(M, seam_spectra(s)), K = seam_rows_before(s), rows = K + S0;
         CopyJob C = {};
