@@ -649,7 +649,7 @@ __device__ __forceinline__ void phase_tables(float2 *ph_hi, float2 *ph_lo, doubl
 // int8 pair store or the pre-quantisation store.  Thread tid finishes channel
 // pairs (2j, 2j+1), j = tid + NT i.  The int8 pairs are stored through the
 // caches: the corner turn reads them next.
-template <int N, int NT, int MODE>
+template <int N, int NT, int MODE, bool UNT_CALC = false>
 __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, const float2 *ph_hi,
                                               const float2 *ph_lo, const float2 *__restrict__ untangle,
                                               const float2 *__restrict__ gn, bool ok, int64_t sp, int tid,
@@ -676,10 +676,25 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
     // overlap instead of adding up channel by channel
     constexpr int P = N / 2 / NT;
     float4 wt[P], gt[P];
+    if constexpr (UNT_CALC) {
+        // (kernels bound by their vector memory instructions) the untangle
+        // twiddles w_k = exp(-i pi k / n) of channels 2 tid + 1 and 2 tid + S i
+        // are w_{2 tid} times the table's w_1 and w_{S i}, whose indices are
+        // the same in every lane (scalar loads)
+        const float2 w0 = untangle[2 * tid];
+        const float2 w1 = cmul(w0, untangle[1]);
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const float2 c = untangle[S * i];
+            const float2 a = i ? cmul(w0, c) : w0, b = i ? cmul(w1, c) : w1;
+            wt[i] = make_float4(a.x, a.y, b.x, b.y);
+        }
+    }
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const int j = tid + NT * i;
-        wt[i] = reinterpret_cast<const float4 *>(untangle)[j];
+        if constexpr (!UNT_CALC)
+            wt[i] = reinterpret_cast<const float4 *>(untangle)[j];
         gt[i] = reinterpret_cast<const float4 *>(gn)[j];
     }
 #pragma unroll
@@ -1902,18 +1917,29 @@ __device__ __forceinline__ void mfma_stage(float2 *__restrict__ buf, typename Mx
         if (P::G % 32 != 0 && gam >= P::G)
             continue;
         // lane holds outputs d = 8 (t / 4) + 4 h + t % 4: re in acc[t], im in acc[t + 8]
+        // twiddles w^d, w = exp(-2 pi i (gam mod R') / 16 R') for this lane's
+        // d = 4h .. 4h+3 and 8+4h .. 11+4h: one load of the table's pair
+        // (w^4h, w^4h+1); w is the second times the conjugate of the first,
+        // w^4 comes from the partner lane (lane ^ 32, same group, other h)
+        // through the LDS crossbar, and the rest follow by products (at most
+        // five deep: rounding near 3e-7, far below the operands' precision)
         float2 tw[8];
         if constexpr (TWID) {
             const float4 *tp = reinterpret_cast<const float4 *>(tw16 + (int64_t(S) * P::G + gam) * 16);
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const float4 w0 = tp[(8 * q + 4 * h) / 2];
-                const float4 w1 = tp[(8 * q + 4 * h) / 2 + 1];
-                tw[4 * q + 0] = make_float2(w0.x, w0.y);
-                tw[4 * q + 1] = make_float2(w0.z, w0.w);
-                tw[4 * q + 2] = make_float2(w1.x, w1.y);
-                tw[4 * q + 3] = make_float2(w1.z, w1.w);
-            }
+            const float4 w0 = tp[2 * h];
+            const float2 a = make_float2(w0.x, w0.y), b = make_float2(w0.z, w0.w);
+            const float2 w = make_float2(b.x * a.x + b.y * a.y, b.y * a.x - b.x * a.y);     // b conj(a)
+            const float2 pa = make_float2(__shfl_xor(a.x, 32), __shfl_xor(a.y, 32));
+            const float2 w4 = h ? a : pa;
+            const float2 w8 = cmul(w4, w4);
+            tw[0] = a;
+            tw[1] = b;
+            tw[2] = cmul(b, w);
+            tw[3] = cmul(tw[2], w);
+            tw[4] = cmul(a, w8);
+            tw[5] = cmul(b, w8);
+            tw[6] = cmul(tw[5], w);
+            tw[7] = cmul(tw[6], w);
         }
         // out(gam, d) = gam + G d, G a multiple of 16 (or the whole array when G = 16)
         const int pw = lds_pad(gam + P::G * 4 * h);
@@ -2048,8 +2074,8 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
         __syncthreads();
     }
 
-    post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
-                               tid, spec8, y_out);
+    post_spectrum<N, NT, MODE, true>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
+                                     tid, spec8, y_out);
 }
 
 // ---------------------------------------------------------------------------
