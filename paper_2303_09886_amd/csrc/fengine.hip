@@ -542,8 +542,14 @@ template <int N> constexpr int lds_len() { return N + N / 16; }
 // polarization's n points held in LDS:
 //   butterfly b: inputs z[b + q n/R], twiddle exp(-2 pi i j q/(L R)) with
 //   j = b mod L, R-point DFT, outputs to (b - j) R + j + r L.
-template <int N, int R, int L>
-__device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, int tp, const float2 *__restrict__ tw)
+// TWL (kernels whose vector memory instructions, not only their arithmetic,
+// bound them): the L = 16 pass reads its 240 twiddles from the LDS copy
+// `tws`, and passes with L > 16 and R = 8 or 16 load w^1 .. w^4, w^8 and w^12
+// (w = exp(-2 pi i j/(L R))) and form the other powers w^(4a + b) = w^4a w^b,
+// one product each.
+template <int N, int R, int L, bool TWL>
+__device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, int tp, const float2 *__restrict__ tw,
+                                         const float2 *__restrict__ tws)
 {
     constexpr int NB = N / R;              // butterflies per polarization
     constexpr int NTP = N / 16;            // threads per polarization
@@ -561,9 +567,32 @@ __device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, int tp, const
     for (int u = 0; u < PER; ++u) {
         const int b = tp + u * NTP;
         const int j = b % L;
+        if constexpr (TWL && L == 16) {
 #pragma unroll
-        for (int q = 1; q < R; ++q)
-            v[u][q] = cmul(v[u][q], tw[(q - 1) * L + j]);
+            for (int q = 1; q < R; ++q)
+                v[u][q] = cmul(v[u][q], tws[(q - 1) * L + j]);
+        } else if constexpr (TWL && R > 4) {
+            // w^1 .. w^4 and w^8, w^12 loaded; w^(4a + b) = w^4a w^b
+            float2 wq[R];
+#pragma unroll
+            for (int q = 1; q <= 4; ++q)
+                wq[q] = tw[(q - 1) * L + j];
+            if constexpr (R > 8) {
+                wq[8] = tw[7 * L + j];
+                wq[12] = tw[11 * L + j];
+            }
+#pragma unroll
+            for (int q = 5; q < R; ++q)
+                if (q % 4 != 0)
+                    wq[q] = cmul(wq[q - q % 4], wq[q % 4]);
+#pragma unroll
+            for (int q = 1; q < R; ++q)
+                v[u][q] = cmul(v[u][q], wq[q]);
+        } else {
+#pragma unroll
+            for (int q = 1; q < R; ++q)
+                v[u][q] = cmul(v[u][q], tw[(q - 1) * L + j]);
+        }
         Dft<R>::run(v[u]);
         const int base = (b - j) * R + j;
 #pragma unroll
@@ -574,16 +603,28 @@ __device__ __forceinline__ void fft_pass(float2 *__restrict__ buf, int tp, const
 }
 
 // Passes 1.. of the plan (pass 0, radix 16 with L = 1, is done by the caller
-// on register-held input).
-template <int N, int P>
-__device__ __forceinline__ void fft_rest(float2 *buf, int tp, const float2 *tw_all)
+// on register-held input).  Every plan's pass 1 is radix 16 with L = 16: its
+// twiddle block is the table's first 240 entries.
+constexpr int TW_PASS1 = 15 * 16;
+
+template <int N, int P, bool TWL = false>
+__device__ __forceinline__ void fft_rest(float2 *buf, int tp, const float2 *tw_all, const float2 *tws = nullptr)
 {
     if constexpr (P < Plan<N>::P) {
         constexpr int R = Plan<N>::R[P];
         constexpr int L = tw_L<N>(P);
-        fft_pass<N, R, L>(buf, tp, tw_all + tw_offset<N>(P));
-        fft_rest<N, P + 1>(buf, tp, tw_all);
+        static_assert(P != 1 || (R == 16 && L == 16 && tw_offset<N>(1) == 0), "pass 1 is radix 16, L = 16");
+        fft_pass<N, R, L, TWL>(buf, tp, tw_all + tw_offset<N>(P), tws);
+        fft_rest<N, P + 1, TWL>(buf, tp, tw_all, tws);
     }
+}
+
+// Copy of the pass-1 twiddles into LDS (read after the caller's next barrier).
+__device__ __forceinline__ void load_tw_pass1(float2 *__restrict__ tws, const float2 *__restrict__ tw_all,
+                                              int tid, int nt)
+{
+    for (int i = tid; i < TW_PASS1; i += nt)
+        tws[i] = tw_all[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -677,16 +718,21 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
     constexpr int P = N / 2 / NT;
     float4 wt[P], gt[P];
     if constexpr (UNT_CALC) {
-        // (kernels bound by their vector memory instructions) the untangle
-        // twiddles w_k = exp(-i pi k / n) of channels 2 tid + 1 and 2 tid + S i
-        // are w_{2 tid} times the table's w_1 and w_{S i}, whose indices are
-        // the same in every lane (scalar loads)
-        const float2 w0 = untangle[2 * tid];
-        const float2 w1 = cmul(w0, untangle[1]);
+        // (the matrix-core kernels, bound by their vector memory
+        // instructions) the untangle twiddles w_k = exp(-i pi k / n) of
+        // channels 2 tid + e + S i are the loaded w_{2 tid + e} times the
+        // table's w_{S i}, whose index is the same in every lane (a scalar
+        // load).  The product's extra rounding shows at the mirror channel of
+        // a strong tone, where the untangle subtracts two terms of the tone's
+        // size: there it reaches 1e-5 of the spectrum's rms, which the FP32
+        // kernels' bound does not leave room for (they load the table).
+        const float4 w01 = reinterpret_cast<const float4 *>(untangle)[tid];
+        const float2 w0 = make_float2(w01.x, w01.y), w1 = make_float2(w01.z, w01.w);
+        wt[0] = w01;
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
+        for (int i = 1; i < P; ++i) {
             const float2 c = untangle[S * i];
-            const float2 a = i ? cmul(w0, c) : w0, b = i ? cmul(w1, c) : w1;
+            const float2 a = cmul(w0, c), b = cmul(w1, c);
             wt[i] = make_float4(a.x, a.y, b.x, b.y);
         }
     }
@@ -736,7 +782,7 @@ __device__ __forceinline__ void post_spectrum(const float2 *__restrict__ buf, co
 template <int N, int MODE>
 __device__ __forceinline__ void fft_post_block(
     int item, bool valid, int tid, float2 *__restrict__ buf, float2 *__restrict__ ph_hi,
-    float2 *__restrict__ ph_lo,
+    float2 *__restrict__ ph_lo, float2 *__restrict__ tws,
     const float *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw_all, const float2 *__restrict__ untangle,
@@ -766,6 +812,7 @@ __device__ __forceinline__ void fft_post_block(
     if (valid && !ok && tid == 0)
         atomicOr(status, 1);
     phase_tables<N, NT>(ph_hi, ph_lo, phases[sp], tau, 0.5f, tid);
+    load_tw_pass1(tws, tw_all, tid, NT);
 
     // forward n-point complex FFT: pass 0 in registers, the rest in LDS
     Dft<16>::run(v);
@@ -773,7 +820,7 @@ __device__ __forceinline__ void fft_post_block(
     for (int r = 0; r < 16; ++r)
         buf[lds_pad(tid * 16 + r)] = v[r];
     __syncthreads();
-    fft_rest<N, 1>(buf, tid, tw_all);
+    fft_rest<N, 1, true>(buf, tid, tw_all, tws);
 
     post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
                                tid, spec8, y_out, valid);
@@ -791,7 +838,8 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
     __shared__ float2 buf[lds_len<N>()];
     __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
     __shared__ float2 ph_lo[64];
-    fft_post_block<N, MODE>(xcd_logical(blockIdx.x, gridDim.x), true, threadIdx.x, buf, ph_hi, ph_lo, g,
+    __shared__ float2 tws[TW_PASS1];
+    fft_post_block<N, MODE>(xcd_logical(blockIdx.x, gridDim.x), true, threadIdx.x, buf, ph_hi, ph_lo, tws, g,
                             delays, phases, gains, tw_all, untangle, spec8, y_out, status, M, D, mb, me);
 }
 
@@ -820,6 +868,7 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_heap
     __shared__ float2 buf[lds_len<N>()];
     __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
     __shared__ float2 ph_lo[64];
+    __shared__ float2 tws[TW_PASS1];
     const int runs = M / SPW;
     const int item = xcd_logical(blockIdx.x, gridDim.x);
     const int a = item / runs;
@@ -830,6 +879,7 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_heap
     // the top and spills); each pass shifts its result in at the end.
     constexpr int Q = 2 * SPW;
     uint32_t q[Q][P];
+    load_tw_pass1(tws, tw_all, int(threadIdx.x), NT);      // read after the first pass's barrier
 #pragma unroll 1
     for (int fp = 0; fp < Q; ++fp) {
         const int f = fp >> 1, p = fp & 1;
@@ -859,7 +909,7 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_heap
         for (int r = 0; r < 16; ++r)
             buf[lds_pad(tid * 16 + r)] = v[r];
         __syncthreads();
-        fft_rest<N, 1>(buf, tid, tw);
+        fft_rest<N, 1, true>(buf, tid, tw, tws);
         uint32_t qn[P];
         post_spectrum<N, NT, OUT_REG>(buf, ph_hi, ph_lo, ut, gains + (int64_t(a) * 2 + p) * N, ok, sp,
                                       tid, nullptr, nullptr, true, qn);
@@ -2074,7 +2124,7 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
         __syncthreads();
     }
 
-    post_spectrum<N, NT, MODE, true>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
+    post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
                                      tid, spec8, y_out);
 }
 
@@ -2223,9 +2273,10 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void post_jobs_ker
     __shared__ float2 buf[lds_len<N>()];
     __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
     __shared__ float2 ph_lo[64];
+    __shared__ float2 tws[TW_PASS1];
     const int b = blockIdx.x;
     const PostJob &J = jobs[find_job(jobs, njobs, b)];
-    fft_post_block<N, OUT_INT8>(b - J.begin, true, threadIdx.x, buf, ph_hi, ph_lo, J.g, J.delays, J.phases,
+    fft_post_block<N, OUT_INT8>(b - J.begin, true, threadIdx.x, buf, ph_hi, ph_lo, tws, J.g, J.delays, J.phases,
                                 J.gains, J.tw, J.untangle, J.spec8, nullptr, J.status, J.M, J.D, 0, J.M);
 }
 
@@ -2702,7 +2753,8 @@ void launch_post_heap_N(const fe_stream *s, const Work &wk, int M, const double 
 
 bool heap_fold(const fe_stream *s)
 {
-    return s->prec == FE_PREC_FP32 && s->n <= 8192 && s->path == FE_PATH_SPLIT_FOLDED;
+    return s->prec == FE_PREC_FP32 && s->n <= 8192 && !fused_path(s)
+           && (s->path == FE_PATH_SPLIT_FOLDED || s->path == FE_PATH_AUTO);
 }
 
 void launch_post_heap(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
