@@ -23,7 +23,6 @@ from __future__ import annotations
 
 import argparse
 import concurrent.futures as cf
-import hashlib
 import json
 import os
 import sys
@@ -54,30 +53,29 @@ def log(*a):
 
 
 def source_hash() -> str:
-    h = hashlib.sha256()
-    for rel in ("paper_2303_09886_amd/csrc/fengine.hip", "include/fengine.h"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    from paper_2303_09886_amd.profsum import source_hash as h
+    return h()
 
 
 def kernel_names(shape: synth.Shape, prec: str, path: str = "split"):
-    """Names of the call's kernels by stage: "fir" is the first kernel (the
-    fused unpack + FIR + FFT + post kernel where the path is fused), "post"
-    the FFT/post kernel of the split path, "turn" the corner turn."""
-    n, T = shape.n, shape.taps
+    """The call's kernels by stage, named as rocprofv3 prints them (template
+    arguments included), so that the counter summary in profiles/ can be
+    looked up: "fir" is the first kernel (the fused unpack + FIR + FFT + post
+    kernel where the path is fused), "post" the FFT/post kernel, "turn" the
+    corner turn (absent where the FFT/post kernel writes the heaps)."""
+    n, T, S = shape.n, shape.taps, shape.spectra_per_heap
     if prec == "fp32":
         tk = next(t for t in (4, 8, 16, 24, 32) if T <= t)
         if path == "fused":
-            return {"fir": "pfb_fused_kernel<%d,%d>" % (n, tk), "turn": "corner_turn_kernel"}
+            return {"fir": "pfb_fused_kernel<%d, %d, 0>" % (n, tk), "turn": "corner_turn_kernel"}
         if path == "split_folded":
-            # the FFT/post kernel writes the heaps itself (no corner-turn launch)
-            return {"fir": "fir_kernel<%d>" % tk, "post": "fft_post_heap_kernel<%d>" % n}
-        return {"fir": "fir_kernel<%d>" % tk, "post": "fft_post_kernel<%d>" % n, "turn": "corner_turn_kernel"}
+            return {"fir": "fir_kernel<%d, 0>" % tk, "post": "fft_post_heap_kernel<%d, %d>" % (n, 2 if S % 2 == 0 else 1)}
+        return {"fir": "fir_kernel<%d, 0>" % tk, "post": "fft_post_kernel<%d, 0>" % n, "turn": "corner_turn_kernel"}
     tk = 16 if T <= 16 else 32
-    fir = ("fir_mfma_kernel<%d,%s>" % (tk, prec) if path == "matrix_fir"
-           else "fir_kernel<%d,%s>" % (tk, "fp16-out" if prec == "fp16" else "fp32-out"))
-    return {"fir": fir, "post": "fft_mfma_kernel<%d,%s>" % (n, prec), "turn": "corner_turn_kernel"}
+    p = 1 if prec == "fp16" else 2
+    fir = ("fir_mfma_kernel<%d, %d, %d>" % (tk, p, 0 if prec == "fp16" else 1) if path == "matrix_fir"
+           else "fir_kernel<%d, %d>" % (next(t for t in (4, 8, 16, 24, 32) if T <= t), 1 if prec == "fp16" else 0))
+    return {"fir": fir, "post": "fft_mfma_kernel<%d, %d, 0>" % (n, p), "turn": "corner_turn_kernel"}
 
 
 def measure(fe, shape, w, sets, dev_arrays, prec, steps, warmup, path="auto"):
@@ -406,7 +404,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=None,
                     help="spectra per antenna for the CPU baseline (default: all)")
-    ap.add_argument("--variants", default="fp16,bf16,fp16_matrix_fir,fused,split_folded,drift",
+    ap.add_argument("--variants", default="fp16,bf16,fp16_matrix_fir,fused,split,drift",
                     help="variants timed beside the FP32 path: fp16, bf16 (DFT stages on the matrix "
                          "cores, vector FIR), fp16_matrix_fir, bf16_matrix_fir (FIR on the matrix cores "
                          "too), split, fused, split_folded (the FP32 stream on those kernel paths), drift (delays "

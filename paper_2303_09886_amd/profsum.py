@@ -1,6 +1,6 @@
 """Summarise rocprofv3 CSV output of a benchmark run into per-kernel tables.
 
-    python -m paper_2303_09886_amd.profsum TRACE_DIR [PMC_DIR ...]
+    python -m paper_2303_09886_amd.profsum [--traffic-json OUT] TRACE_DIR [PMC_DIR ...]
 
 TRACE_DIR holds a ``--kernel-trace --output-format csv`` run
 (``*_kernel_trace.csv``); each PMC_DIR a ``--pmc ... --output-format csv`` run
@@ -11,17 +11,34 @@ the mean of every counter per dispatch.  HBM bytes are scaled with the
 plain device copy of the run (the largest ``__amd_rocclr_copyBuffer``
 dispatch, 512 MiB read and 512 MiB written), which reads what FETCH_SIZE and
 WRITE_SIZE (KiB) mean on this GPU.
+
+--traffic-json OUT writes, for each kernel, the HBM bytes per launch of its
+largest-grid dispatches (the benchmark's large workload) with the hash of
+the kernel source they were taken on; bench.py reports them as the roofline's
+`traffic` while that source is unchanged.
 """
 from __future__ import annotations
 
 import collections
 import csv
 import glob
+import hashlib
+import json
 import os
 import re
 import sys
 
 COPY_BYTES = 512 << 20
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def source_hash() -> str:
+    """Hash of the kernel source and its C header (first 16 hex digits)."""
+    h = hashlib.sha256()
+    for rel in ("paper_2303_09886_amd/csrc/fengine.hip", "include/fengine.h"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def short(name: str) -> str:
@@ -51,6 +68,12 @@ def load_pmc(dirs):
 
 
 def main(argv):
+    argv = list(argv)
+    out_json = None
+    if "--traffic-json" in argv:
+        i = argv.index("--traffic-json")
+        out_json = argv[i + 1]
+        del argv[i:i + 2]
     if not argv:
         print(__doc__)
         return 1
@@ -92,11 +115,40 @@ def main(argv):
             derived.append("%.0f kernel cycles per XCD" % cyc)
         if "SQ_INSTS_VALU" in c and "SQ_WAVE_CYCLES" in c and c["SQ_WAVE_CYCLES"] > 0:
             derived.append("wait share %.0f%% of wave cycles" % (100 * c.get("SQ_WAIT_INST_ANY", 0) / c["SQ_WAVE_CYCLES"]))
+        if "TA_BUSY_avr" in c and "GRBM_GUI_ACTIVE" in c and c["GRBM_GUI_ACTIVE"] > 0:
+            derived.append("TA (address unit) busy %.0f%% of kernel cycles"
+                           % (100 * c["TA_BUSY_avr"] / (c["GRBM_GUI_ACTIVE"] / 8.0)))
+        if "SQ_INSTS_VALU" in c and "GRBM_GUI_ACTIVE" in c and c["GRBM_GUI_ACTIVE"] > 0:
+            derived.append("VALU issue %.2f per CU-cycle"
+                           % (c["SQ_INSTS_VALU"] / (256 * c["GRBM_GUI_ACTIVE"] / 8.0)))
         if "SQ_INSTS_LDS" in c and c.get("SQ_INSTS_LDS", 0) > 0:
             derived.append("LDS bank-conflict cycles per LDS instruction %.2f"
                            % (c.get("SQ_LDS_BANK_CONFLICT", 0) / c["SQ_INSTS_LDS"]))
         if derived:
             print("   -> " + "; ".join(derived))
+    if out_json:
+        if not (fetch_f and write_f):
+            print("no copy calibration in the counter runs: no traffic summary written")
+            return 1
+        kernels = {}
+        for (name, grid), c in pmc.items():
+            if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c or name.startswith(("__amd", "at::")):
+                continue
+            if name in kernels and kernels[name]["grid"] >= grid:
+                continue
+            fk = sum(c["FETCH_SIZE"]) / len(c["FETCH_SIZE"])
+            wk = sum(c["WRITE_SIZE"]) / len(c["WRITE_SIZE"])
+            d = trace.get((name, grid), [])
+            kernels[name] = {"grid": grid, "fetch_kib": fk, "write_kib": wk,
+                             "read_bytes": fk * 1024 * fetch_f, "write_bytes": wk * 1024 * write_f,
+                             "bytes_per_launch": int(fk * 1024 * fetch_f + wk * 1024 * write_f),
+                             "mean_ms": sum(d) / len(d) / 1e6 if d else None}
+        rec = {"source_hash": source_hash(),
+               "calibration": {"copy_bytes": COPY_BYTES, "fetch_factor": fetch_f, "write_factor": write_f},
+               "kernels": dict(sorted(kernels.items()))}
+        with open(out_json, "w") as f:
+            json.dump(rec, f, indent=1)
+        print("wrote %s (%d kernels)" % (out_json, len(kernels)))
     return 0
 
 
