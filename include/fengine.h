@@ -252,10 +252,12 @@ enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2, FE_PATH_MATRIX_FI
  *   spectra and writes every channel's bytes straight into the heap (Sec.
  *   3.6 turns inside its post-processing kernel too): 2 bytes per sample
  *   less device-memory traffic, one launch fewer.
- * FE_PATH_AUTO: fused for FP32 streams with T <= 8 and n <= 2048, else
- *   split with the turn folded (FP32, n <= 8192: as fast as the separate
- *   turn on MI355X, with 2 bytes per sample less traffic) or split (the
- *   fastest for those shapes; for FP16/BF16 streams the vector FIR).
+ * FE_PATH_AUTO: fused for FP32 streams with T <= 8 and n <= 2048; split
+ *   with the turn folded for other FP32 streams with n <= 8192 whose calls
+ *   give the folded kernel at least 8 workgroups per compute unit (as fast
+ *   as the separate turn on MI355X, with 2 bytes per sample less traffic);
+ *   else split (for FP16/BF16 streams with the vector FIR).  The schedule
+ *   reported for FE_PATH_AUTO is that of a call of max_samples.
  * Streams the fused path cannot run always run the split path (the setting
  * is kept).  fir_batches as in fe_stream_set_tuning; on the fused path it
  * caps the kernel's workgroups per compute unit (0 = as many as fit).

@@ -2751,10 +2751,19 @@ void launch_post_heap_N(const fe_stream *s, const Work &wk, int M, const double 
                            s->d_untangle, out, s->d_status, M, s->D, s->S);
 }
 
-bool heap_fold(const fe_stream *s)
+// Whether a call of M spectra runs the folded FFT/post kernel.  FE_PATH_AUTO
+// folds only when the folded launch (a workgroup per antenna and run of one
+// or two spectra) still gives every CU eight workgroups: on fewer it is
+// slower than the split kernel's workgroup per spectrum and polarization
+// plus the separate turn.
+bool heap_fold(const fe_stream *s, int M)
 {
-    return s->prec == FE_PREC_FP32 && s->n <= 8192 && !fused_path(s)
-           && (s->path == FE_PATH_SPLIT_FOLDED || s->path == FE_PATH_AUTO);
+    if (s->prec != FE_PREC_FP32 || s->n > 8192 || fused_path(s))
+        return false;
+    if (s->path == FE_PATH_SPLIT_FOLDED)
+        return true;
+    const int spw = s->S % 2 == 0 ? 2 : 1;
+    return s->path == FE_PATH_AUTO && int64_t(s->A) * (M / spw) >= int64_t(8) * s->cus;
 }
 
 void launch_post_heap(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
@@ -3052,7 +3061,7 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
     launch_history_update(s, wk, raw, N);
     mark(2);
     // int8 output on the FP32 split path: the FFT/post kernel writes the heaps
-    const bool heap = !g_out && !y_out && !fused && heap_fold(s);
+    const bool heap = !g_out && !y_out && !fused && heap_fold(s, M);
     if (heap)
         launch_post_heap(s, wk, M, delays, phases, gains, out);
     else if (!g_out && !fused)
@@ -3492,7 +3501,7 @@ fe_status fe_stream_get_schedule(const fe_stream *s, int *path, int *fir_batches
         return FE_EINVAL;
     if (path)
         *path = fused_path(s) ? FE_PATH_FUSED : matrix_fir(s) ? FE_PATH_MATRIX_FIR
-                : heap_fold(s) ? FE_PATH_SPLIT_FOLDED : FE_PATH_SPLIT;
+                : heap_fold(s, int(s->max_samples / (2 * s->n))) ? FE_PATH_SPLIT_FOLDED : FE_PATH_SPLIT;
     if (fir_batches)
         *fir_batches = s->fir_batches;
     return FE_OK;
