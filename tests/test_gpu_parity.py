@@ -288,9 +288,12 @@ def test_prequant_matches_oracle(n, T, A, S, M, calls):
 # odd heap sizes: heaps of 3 and 1 spectra (the FFT/post kernel then writes
 # one spectrum's bytes per channel at a time)
 ODD_HEAPS = [(1024, 16, 2, 3, 33, 2), (8192, 8, 1, 1, 7, 1)]
+# the two-level FFT's rounds split over 3 workgroups (128 spectra-pols) and
+# kept in one (512)
+TWO_LEVEL_SPLITS = [(16384, 8, 1, 4, 64, 1), (16384, 16, 2, 2, 128, 1)]
 
 
-@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10] + CASES[13:15] + ODD_HEAPS)
+@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10] + CASES[13:15] + ODD_HEAPS + TWO_LEVEL_SPLITS)
 def test_int8_matches_oracle(n, T, A, S, M, calls):
     _say("int8 n=%d T=%d A=%d S=%d M=%d calls=%d" % (n, T, A, S, M, calls))
     shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
