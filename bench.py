@@ -151,12 +151,14 @@ def stored_traffic(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def measure_batch(fe, steps: int, warmup: int, tune: bool = True):
+def measure_batch(fe, steps: int, warmup: int, tune: bool = True, precision: str = "fp32"):
     """The 16-stream uneven batch: every step runs one call of each stream.
     Timed as one graph launch per step with the launches grouped across the
     members (job-list kernels), as one graph launch per step with every
     member's kernels on a fork stream of its own, and as the same calls
-    issued stream after stream on one HIP stream (no overlap)."""
+    issued stream after stream on one HIP stream (no overlap).  With
+    `precision` fp16 or bf16 the members of up to 8192 channels run in that
+    precision (the larger ones in FP32, the only precision above 8192)."""
     import torch
     shapes = synth.BATCH16
     streams, bufs = [], []
@@ -164,7 +166,7 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True):
         w = synth.make_workload(sh, 100 + i, delay_rate=SIDEREAL_RATE)
         M = sh.samples // (2 * sh.n)
         st = fe.Stream(sh.n, sh.taps, 1, w.weights, sh.samples, spectra_per_heap=sh.spectra_per_heap,
-                       max_delay=sh.max_delay)
+                       max_delay=sh.max_delay, precision=precision if sh.n <= 8192 else "fp32")
         out = torch.empty((1, M // sh.spectra_per_heap, sh.n, sh.spectra_per_heap, 2, 2),
                           dtype=torch.int8, device="cuda")
         b = [torch.from_numpy(w.raw).cuda(), sh.samples, torch.from_numpy(w.delays).cuda(),
@@ -207,19 +209,22 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True):
         if st.status() != fe.FE_OK:
             log("warning: batch member status %d" % st.status())
         st.close()
-    g_ms = res[True]
-    return {"value": round(total / (g_ms * 1e-3) / 1e9, 2), "unit": "Gsample/s", "ms_per_step": round(g_ms, 4),
-            "per_member_launches_ms_per_step": round(res[False], 4),
-            "per_member_launches_value": round(total / (res[False] * 1e-3) / 1e9, 2),
+    m_ms, g_ms = res[False], res[True]
+    return {"value": round(total / (m_ms * 1e-3) / 1e9, 2), "unit": "Gsample/s", "ms_per_step": round(m_ms, 4),
+            "issued": "per-member fork streams (the batch default)",
+            "grouped_launches_ms_per_step": round(g_ms, 4),
+            "grouped_launches_value": round(total / (g_ms * 1e-3) / 1e9, 2),
             "sequential_ms_per_step": round(seq_ms, 4),
             "sequential_value": round(total / (seq_ms * 1e-3) / 1e9, 2),
             "streams": len(shapes), "samples_per_step": total,
-            "tuned_schedule": {"knobs": ["path (split|fused)", "fir_batches (FIR run length in batches of "
+            "tuned_schedule": {"knobs": ["path (split|split_folded|fused|matrix_fir)", "fir_batches (FIR run length in batches of "
                                          "spectra, or fused workgroups per CU; 0 = per-launch default)"],
                                "per_stream": choices},
+            "precision": precision if precision == "fp32" else precision + " (members of up to 8192 channels)",
             "config": "16 single-antenna streams, channels 1024/4096/8192/32768, taps 8/16/24, "
-                      "2^22..2^24 samples/pol each, heaps of 64 spectra, one HIP-graph launch per step "
-                      "(FP32 split-path members through job-list kernels grouped by tap count and channel count)"}
+                      "2^22..2^24 samples/pol each, heaps of 64 spectra, one HIP-graph launch per step; "
+                      "grouped: FP32 split-path members through job-list kernels grouped by tap count and "
+                      "channel count"}
 
 
 def measure_service(chunks: int = 24, seed: int = 3):
@@ -478,6 +483,8 @@ def main():
         torch.cuda.empty_cache()
         log("batch: 16 uneven streams")
         batched = measure_batch(fe, max(5, args.steps // 5), 2)
+        log("batch: 16 uneven streams, FP16 where the channel count allows")
+        batched["fp16"] = measure_batch(fe, max(5, args.steps // 5), 2, precision="fp16")
 
     streaming = None
     if not args.no_service:

@@ -879,6 +879,11 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_heap
     // the top and spills); each pass shifts its result in at the end.
     constexpr int Q = 2 * SPW;
     uint32_t q[Q][P];
+#pragma unroll
+    for (int u = 0; u < Q; ++u)
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            q[u][i] = 0u;
     load_tw_pass1(tws, tw_all, int(threadIdx.x), NT);      // read after the first pass's barrier
 #pragma unroll 1
     for (int fp = 0; fp < Q; ++fp) {
@@ -3945,7 +3950,7 @@ fe_status fe_batch_create(fe_stream *const *members, int count, void *hip_stream
     b->d_jobs_graph = b->d_jobs_eager = b->h_jobs = nullptr;
     b->upload_ev = nullptr;
     b->upload_pending = false;
-    b->grouped = true;
+    b->grouped = false;                    // per-member fork streams measure faster
     for (int k = 0; k < 6; ++k) {
         b->gs[k] = nullptr;
         b->gev[k] = nullptr;

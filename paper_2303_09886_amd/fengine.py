@@ -359,7 +359,7 @@ class Batch:
         _check(load_library().fe_batch_launch(self._h), "fe_batch_launch")
 
     def set_grouped(self, grouped: bool):
-        """fe_batch_set_grouped: grouped launches (default) or every member on its own fork stream."""
+        """fe_batch_set_grouped: grouped launches, or every member on its own fork stream (default)."""
         _check(load_library().fe_batch_set_grouped(self._h, 1 if grouped else 0), "fe_batch_set_grouped")
 
     def close(self):

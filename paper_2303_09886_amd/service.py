@@ -243,6 +243,9 @@ class Service:
             raise state["error"]
         wall = max(r.done for r in requests) if requests else 0.0
         lat = np.array([r.latency for r in requests]) * 1e3
+        # latency per 2^20 samples of the chunk: chunks of different sizes
+        # take different times even alone, this spread is the scheduling's
+        per_m = lat / np.array([r.n_samples / float(1 << 20) for r in requests])
         samples = 2 * sum(r.n_samples for r in requests)
         for st in self.streams:
             if st.status() != fengine.FE_OK:
@@ -251,7 +254,10 @@ class Service:
                 "gsamples_per_s": samples / wall / 1e9,
                 "latency_ms_p50": float(np.percentile(lat, 50)),
                 "latency_ms_p99": float(np.percentile(lat, 99)),
-                "latency_ms_max": float(lat.max()), "peak_inflight_bytes": state["peak"]}
+                "latency_ms_max": float(lat.max()),
+                "latency_ms_per_2e20_samples_p50": float(np.percentile(per_m, 50)),
+                "latency_ms_per_2e20_samples_p99": float(np.percentile(per_m, 99)),
+                "peak_inflight_bytes": state["peak"]}
 
     def _slot_locked(self, cond):
         with cond:

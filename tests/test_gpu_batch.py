@@ -118,9 +118,11 @@ def test_batch_graph_and_eager_match_streams_alone(grouped):
              % (mode, grouped, len(SHAPES), STEPS))
 
 
-def test_every_batch_member_matches_oracle():
-    """Each member's output from the graph-replayed batch (grouped launches),
-    over both steps, against the FP64 oracle: the int8 rule of
+@pytest.mark.parametrize("grouped", [True, False])
+def test_every_batch_member_matches_oracle(grouped):
+    """Each member's output from the graph-replayed batch (grouped launches
+    and per-member fork streams), over both steps, against the FP64 oracle:
+    the int8 rule of
     test_gpu_parity for FP32 members, within 1 LSB for the FP16/BF16
     members (the matrix-core bar of test_gpu_mfma)."""
     members = [make(s, p) for s, p in zip(SHAPES, PRECS)]
@@ -129,6 +131,7 @@ def test_every_batch_member_matches_oracle():
         raw, d, p, g = step_inputs(shape, 0)
         bufs.append([dev(raw), shape.samples, dev(d), dev(p), dev(g), out_like(shape)])
     batch = fe.Batch(members)
+    batch.set_grouped(grouped)
     batch.capture(bufs)
     outs = [[] for _ in SHAPES]
     for k in range(STEPS):
