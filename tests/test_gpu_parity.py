@@ -165,6 +165,34 @@ def test_hot_path_unpack_every_code_and_phase(prec):
     assert np.array_equal(ref["g"][1, 0, 40], x[1, 0, 2 * n * 40 - int(w.delays[1, 0, 40]) + np.arange(2 * n)])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_hot_path_unpack_at_zero_delay(prec):
+    """With coarse delay 0 the last column pair of a region's last row ends at
+    its last byte, where the FIR reads that pair's word a byte early and
+    shifts it back (a whole-word load would pass the end): every code at every
+    bit phase again, all delays 0, over the call's own rows and the history
+    seam."""
+    _say("hot-path unpack at zero delay %s" % prec)
+    n, S, M, calls = 256, 4, 32, 3
+    shape = synth.Shape(n=n, taps=1, antennas=2, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 12, total=2 * n * M * calls)
+    i = np.arange(w.total)
+    x = np.empty_like(w.x)
+    for a in range(2):
+        for p in range(2):
+            x[a, p] = (i + 311 * (2 * a + p)) % 1025 % 1024 - 512
+    w.x, w.raw = x, synth.pack10(x)
+    w.weights = np.ones_like(w.weights)
+    w.delays[:] = 0.0
+    path = PATH["now"] if prec == "fp32" else {"fused": "matrix_fir"}.get(PATH["now"], "split")
+    st = fe.Stream(n, 1, 2, w.weights, 2 * n * M, spectra_per_heap=S, precision=prec, path=path)
+    g, status = gpu_run(w, 2 * n * M, mode="fir", stream=st)
+    st.close()
+    assert status == fe.FE_OK
+    ref = oracle_run(w, want=("g",))
+    assert np.array_equal(g, ref["g"].astype(np.float32))
+
+
 # --------------------------------------------------------------------------
 # Steps 1-3a: FIR output with impulses is exact; with noise within 1e-5
 # --------------------------------------------------------------------------
