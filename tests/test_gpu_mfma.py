@@ -12,9 +12,12 @@ test_gpu_parity):
   bounded: FP16 rounding inside the FFT is proportional to the values it
   rounds, so bins next to a strong tone carry a share of the tone's rounding
   error (the data-dependent spurs of Sec. 3.5.1);
-* int8: |q - q_ref| <= 1 everywhere (the count of differing values is
-  printed).
+* int8: |q - q_ref| <= 1 everywhere on the small and sampled configurations
+  (the count of differing values is printed); over every value of the
+  benchmark workload, BF16 <= 1 and FP16 <= 2, the 2-LSB values (at most one
+  in a million) lying at the rounding spurs of a strong tone (Sec. 3.5.1).
 """
+import os
 import sys
 
 import numpy as np
@@ -34,6 +37,7 @@ import paper_2303_09886_amd as fe   # noqa: E402
 
 PRECS = ["fp16", "bf16"]
 FIR_RTOL = {"fp16": 1e-3, "bf16": 1e-5}
+INT8_FULL_LSB = {"fp16": 2, "bf16": 1}      # over every value of the benchmark workload
 Y_NORMWISE = 2e-3
 
 
@@ -317,29 +321,46 @@ def test_out_of_range_delay(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_large_config_sampled(prec):
+def test_large_config_every_spectrum(prec):
     """4 antennas x 2 pols, 2^24 samples/pol, 4096 channels, 16 taps, in the
-    benchmark's launch configuration; sampled spectra against the oracle."""
-    _say("mfma %s large config, sampled" % prec)
+    benchmark's launch configuration: every spectrum against the oracle
+    (int8 within 1 LSB, pre-quantisation normwise bar), the oracle per
+    antenna and heap on a thread pool."""
+    import concurrent.futures as cf
+    _say("mfma %s large config, every spectrum" % prec)
     w = synth.make_workload(synth.LARGE, 2)
     shape = w.shape
-    S, n = shape.spectra_per_heap, shape.n
+    S, n, A = shape.spectra_per_heap, shape.n, shape.antennas
+    M = w.total // (2 * n)
     q, status = gpu_run(w, w.total, prec, mode="int8")
     assert status == fe.FE_OK
-    worst = 0
-    for F in (0, 1, 15, 16, 255, 256, 1000, 2047):
-        ref = oracle.channelize(w.raw, w.total, n, shape.taps, 128, w.weights, w.delays,
-                                w.phases, w.gains, F, F + 1, want=("q",))
-        got = q[:, F // S, :, F % S].astype(np.int16)
-        q_ref = ref["q"][:, :, 0].transpose(0, 2, 1, 3).astype(np.int16)
-        worst = max(worst, int(np.abs(got - q_ref).max()))
-    _say("  large %s: int8 max |dq| %d" % (prec, worst))
-    assert worst <= 1
-    y, _ = gpu_run(w, w.total, prec, mode="prequant")
-    for F in (0, 16, 1024, 2047):
-        ref = oracle.channelize(w.raw, w.total, n, shape.taps, 128, w.weights, w.delays,
-                                w.phases, w.gains, F, F + 1, want=("y",))
-        check_y(y[:, :, F:F + 1], ref["y"], "%s large F=%d" % (prec, F))
+    y, status = gpu_run(w, w.total, prec, mode="prequant")
+    assert status == fe.FE_OK
+
+    def check(task):
+        a, h = task
+        F0, F1 = h * S, (h + 1) * S
+        ref = oracle.channelize(w.raw[a:a + 1], w.total, n, shape.taps, 128, w.weights, w.delays[a:a + 1],
+                                w.phases[a:a + 1], w.gains[a:a + 1], F0, F1, want=("y", "q"))
+        d = np.abs(q[a:a + 1, h:h + 1].astype(np.int16) - oracle.heap_layout(ref["q"], S).astype(np.int16))
+        nw, _ = compare.prequant_errors(y[a:a + 1, :, F0:F1], ref["y"])
+        return int(d.max()), int((d > 0).sum()), nw, int((d > 1).sum()), d.size
+
+    tasks = [(a, h) for a in range(A) for h in range(M // S)]
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        res = list(ex.map(check, tasks))
+    worst = max(r[0] for r in res)
+    differ = sum(r[1] for r in res)
+    nw = max(r[2] for r in res)
+    two = sum(r[3] for r in res)
+    size = sum(r[4] for r in res)
+    _say("  large %s: int8 max |dq| %d (%d values differ, %d by 2), Y normwise %.3g" % (prec, worst, differ, two, nw))
+    # FP16 operands: at the rounding spurs of a strong tone (Sec. 3.5.1) a
+    # value can miss by 2 LSB (18 of 268 million here, in one channel, a
+    # third of the tone's); BF16 hi + lo: 1 LSB everywhere
+    assert worst <= INT8_FULL_LSB[prec]
+    assert two <= size * 1e-6
+    assert nw <= Y_NORMWISE
 
 
 # --------------------------------------------------------------------------
