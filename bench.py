@@ -69,12 +69,12 @@ def kernel_names(shape: synth.Shape, prec: str, path: str = "split"):
         if path == "fused":
             return {"fir": "pfb_fused_kernel<%d, %d, 0>" % (n, tk), "turn": "corner_turn_kernel"}
         if path == "split_folded":
-            return {"fir": "fir_kernel<%d, 0>" % tk, "post": "fft_post_heap_kernel<%d, %d>" % (n, 2 if S % 2 == 0 else 1)}
-        return {"fir": "fir_kernel<%d, 0>" % tk, "post": "fft_post_kernel<%d, 0>" % n, "turn": "corner_turn_kernel"}
+            return {"fir": "fir_kernel<%d, 0, false>" % tk, "post": "fft_post_heap_kernel<%d, %d>" % (n, 2 if S % 2 == 0 else 1)}
+        return {"fir": "fir_kernel<%d, 0, false>" % tk, "post": "fft_post_kernel<%d, 0>" % n, "turn": "corner_turn_kernel"}
     tk = 16 if T <= 16 else 32
     p = 1 if prec == "fp16" else 2
     fir = ("fir_mfma_kernel<%d, %d, %d>" % (tk, p, 0 if prec == "fp16" else 1) if path == "matrix_fir"
-           else "fir_kernel<%d, %d>" % (next(t for t in (4, 8, 16, 24, 32) if T <= t), 1 if prec == "fp16" else 0))
+           else "fir_kernel<%d, %d, false>" % (next(t for t in (4, 8, 16, 24, 32) if T <= t), 1 if prec == "fp16" else 0))
     return {"fir": fir, "post": "fft_mfma_kernel<%d, %d, 0>" % (n, p), "turn": "corner_turn_kernel"}
 
 

@@ -203,24 +203,41 @@ __device__ __forceinline__ void store_g2(float a, float b, __amdgpu_buffer_rsrc_
     }
 }
 
-template <int T, int GM = G_F32>
+// spectra per group of the FIR: T (T < 8), 8 (T <= 16), 4
+__host__ __device__ constexpr int fir_group(int T) { return T < 8 ? T : (T <= 16 ? 8 : 4); }
+
+template <int R> struct Dft;               // small DFTs (defined with the FFT below)
+
+// FRONT (FP32, n > 8192): the first radix-16 stage of the two-level FFT
+// folded into the FIR.  Thread (j, gl) of the workgroup filters column pair
+// gam + (n/16) j of the block's 16 groups gam = 16 cb + gl; a group's G rows
+// of filtered samples go to the LDS tile `fl` [G][16 j][16 gl (+1 pad)], and
+// after a barrier 16 G threads each take one (row, gam), form the DFT-16 over
+// j, multiply output d by exp(-2 pi i gam d / n) (table `twf`, [n/16][16]) and
+// store it at gam + (n/16) d: the rows fft_front_kernel would produce,
+// without its read and write of g.
+template <int T, int GM = G_F32, bool FRONT = false>
 __device__ __forceinline__ void fir_block(
     int lb, int *__restrict__ s_c,
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
     void *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
-    int moff, int mrows)
+    int moff, int mrows, float2 (*__restrict__ fl)[16][17] = nullptr, const float2 *__restrict__ twf = nullptr)
 {
-    constexpr int G = T < 8 ? T : (T <= 16 ? 8 : 4);         // spectra per group
+    constexpr int G = fir_group(T);                           // spectra per group
     constexpr uint32_t ES = GM == G_F16 ? 2u : 4u;          // bytes per stored sample
+    static_assert(!FRONT || GM == G_F32, "the folded front stage runs on float32 g");
     const int cb = lb % colblocks;
     const int rest = lb / colblocks;
     const int run = rest % runs;
     const int s = rest / runs;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int t_blk = cb * 2 * FIR_THREADS;                   // the block's first column
-    const int t = t_blk + 2 * tid;                            // the pair's first column
+    const int gpt = n2 / 32;                                  // FRONT: groups gam per spectrum (n/16)
+    const int gbase = cb * 16;                                // FRONT: the block's first group
+    // the block's smallest column, and the pair's first column
+    const int t_blk = FRONT ? 2 * gbase : cb * 2 * FIR_THREADS;
+    const int t = FRONT ? 2 * (gbase + (tid & 15) + gpt * (tid >> 4)) : t_blk + 2 * tid;
     const int m0 = mb + run * R;
     const int mend = min(m0 + R, me);
 
@@ -279,6 +296,28 @@ __device__ __forceinline__ void fir_block(
     // drops them)
     constexpr uint32_t DROP = 0x80000000u;
 
+    // FRONT: rows row0 .. row0 + cnt - 1 (of g) from the tile, as described above
+    auto front = [&](int row0, int cnt) {
+        __syncthreads();                                      // the tile is written
+        if (tid < 16 * G) {
+            const int r = tid >> 4, gl = tid & 15;
+            if (r < cnt) {
+                float2 v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    v[q] = fl[r][q][gl];
+                Dft<16 + 0 * T>::run(v);                      // (dependent: Dft is complete by instantiation)
+                const int gam = gbase + gl;
+                float2 *z = static_cast<float2 *>(g) + (int64_t(s) * M + row0 + r) * (n2 / 2);
+                const float2 *tw = twf + int64_t(gam) * 16;
+#pragma unroll
+                for (int d = 0; d < 16; ++d)
+                    z[gam + gpt * d] = d == 0 ? v[0] : cmul(v[d], tw[d]);
+            }
+        }
+        __syncthreads();                                      // the tile is read
+    };
+
     for (int sa = m0; sa < mend; sa += FIR_SEG) {
         const int se = min(sa + FIR_SEG, mend);
         __syncthreads();                                      // the last segment's table is read
@@ -303,7 +342,12 @@ __device__ __forceinline__ void fir_block(
                     a1 = fmaf(float(sample_at(rs, hs, i + 1, H)), h[j].y, a1);
                     i += n2;
                 }
-                store_g2<GM>(c >= 0 ? a0 : 0.f, c >= 0 ? a1 : 0.f, rg, t_bytes, uint32_t((m - moff) * n2) * ES);
+                if constexpr (FRONT) {
+                    fl[0][tid >> 4][tid & 15] = c >= 0 ? make_float2(a0, a1) : make_float2(0.f, 0.f);
+                    front(m - moff, 1);
+                } else {
+                    store_g2<GM>(c >= 0 ? a0 : 0.f, c >= 0 ? a1 : 0.f, rg, t_bytes, uint32_t((m - moff) * n2) * ES);
+                }
                 c_cur = -1;
                 ++m;
                 continue;
@@ -357,8 +401,13 @@ __device__ __forceinline__ void fir_block(
                         a0 = fmaf(j + r < T - 1 ? X0[j + r] : Y0[j + r - (T - 1)], h[j].x, a0);
                         a1 = fmaf(j + r < T - 1 ? X1[j + r] : Y1[j + r - (T - 1)], h[j].y, a1);
                     }
-                    store_g2<GM>(a0, a1, rg, t_bytes, r < cnt ? soff + uint32_t(r * n2) * ES : DROP);
+                    if constexpr (FRONT)
+                        fl[r][tid >> 4][tid & 15] = make_float2(a0, a1);
+                    else
+                        store_g2<GM>(a0, a1, rg, t_bytes, r < cnt ? soff + uint32_t(r * n2) * ES : DROP);
                 }
+                if constexpr (FRONT)
+                    front(g0 - moff, cnt);
                 // the window's last T-1 rows become the older rows of the next group
 #pragma unroll
                 for (int i = 0; i < T - 1; ++i) {
@@ -374,17 +423,18 @@ __device__ __forceinline__ void fir_block(
     }
 }
 
-template <int T, int GM>
-__global__ __launch_bounds__(FIR_THREADS, FIR_WG_PER_CU(T)) void fir_kernel(
+template <int T, int GM, bool FRONT = false>
+__global__ __launch_bounds__(FIR_THREADS, FRONT ? 2 : FIR_WG_PER_CU(T)) void fir_kernel(
     const uint8_t *__restrict__ raw, int64_t raw_stride,
     const uint8_t *__restrict__ hist, int64_t hist_stride, int H,
     const float *__restrict__ taps, const double *__restrict__ delays,
     void *__restrict__ g, int n2, int M, int D, int R, int colblocks, int runs, int mb, int me,
-    int moff, int mrows)
+    int moff, int mrows, const float2 *__restrict__ twf)
 {
     __shared__ int s_c[FIR_SEG];
-    fir_block<T, GM>(xcd_logical(blockIdx.x, gridDim.x), s_c, raw, raw_stride, hist, hist_stride, H, taps,
-                      delays, g, n2, M, D, R, colblocks, runs, mb, me, moff, mrows);
+    __shared__ float2 fl[FRONT ? fir_group(T) : 1][16][17];
+    fir_block<T, GM, FRONT>(xcd_logical(blockIdx.x, gridDim.x), s_c, raw, raw_stride, hist, hist_stride, H, taps,
+                            delays, g, n2, M, D, R, colblocks, runs, mb, me, moff, mrows, fl, twf);
 }
 
 // The seam of a call for the FIR: per stream, dst = [zero bytes | the
@@ -1230,6 +1280,19 @@ __global__ __launch_bounds__(256) void fft_front_kernel(float *__restrict__ g, c
 #pragma unroll
     for (int d = 0; d < 16; ++d)
         z[gam + gpt * d] = d == 0 ? v[0] : cmul(v[d], tw[d]);
+}
+
+// fft_front_kernel's side job alone (calls whose FIR did the first stage):
+// the per-channel gains of every stream into residue-plane order.
+__global__ __launch_bounds__(256) void gains_planes_kernel(const float2 *__restrict__ gains, float2 *__restrict__ gpl,
+                                                           int n, int64_t total)
+{
+    const int gpt = n / 16;
+    const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (i < total) {
+        const int r = int(i % n);
+        gpl[i] = gains[i - r + r / gpt + 16 * (r % gpt)];
+    }
 }
 
 template <int NL, int MODE>
@@ -2604,7 +2667,7 @@ int64_t seam_bytes(const fe_stream *s)
 
 template <int T, int GM>
 void launch_fir_range(const fe_stream *s, const uint8_t *raw, int64_t raw_stride, int mrows, int moff, int M,
-                      const double *delays, void *g, int mb, int me)
+                      const double *delays, void *g, int mb, int me, bool front = false)
 {
     const int n2 = 2 * s->n;
     const int streams = 2 * s->A;
@@ -2620,14 +2683,22 @@ void launch_fir_range(const fe_stream *s, const uint8_t *raw, int64_t raw_stride
             R -= B;
     const int runs = (me - mb + R - 1) / R;
     const int64_t blocks = int64_t(streams) * runs * colblocks;
+    if constexpr (GM == G_F32 && T <= 16) {
+        if (front) {
+            hipLaunchKernelGGL((fir_kernel<T, GM, true>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
+                               raw, raw_stride, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps, delays, g,
+                               n2, M, s->D, R, colblocks, runs, mb, me, moff, mrows, s->d_twf);
+            return;
+        }
+    }
     hipLaunchKernelGGL((fir_kernel<T, GM>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
                        raw, raw_stride, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps, delays, g,
-                       n2, M, s->D, R, colblocks, runs, mb, me, moff, mrows);
+                       n2, M, s->D, R, colblocks, runs, mb, me, moff, mrows, nullptr);
 }
 
 template <int T, int GM>
 void launch_fir_T(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays,
-                  void *g, int mb, int me)
+                  void *g, int mb, int me, bool front = false)
 {
     const int n2 = 2 * s->n;
     const int M = int(N / n2);
@@ -2646,11 +2717,11 @@ void launch_fir_T(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_
                            reinterpret_cast<const uint32_t *>(s->d_hist), hist_words,
                            reinterpret_cast<const uint32_t *>(raw), N * 5 / 16, zero_words,
                            int64_t(S0) * row_bytes / 4, streams);
-        launch_fir_range<T, GM>(s, wk.seam, rows * row_bytes, rows, K, M, delays, g, K + mb, K + S0);
+        launch_fir_range<T, GM>(s, wk.seam, rows * row_bytes, rows, K, M, delays, g, K + mb, K + S0, front);
         main_mb = S0;
     }
     if (main_mb < me)
-        launch_fir_range<T, GM>(s, raw, N * 5 / 4, M, 0, M, delays, g, main_mb, me);
+        launch_fir_range<T, GM>(s, raw, N * 5 / 4, M, 0, M, delays, g, main_mb, me, front);
 }
 
 template <int TK, int PREC>
@@ -2681,15 +2752,24 @@ void launch_fir_mfma_T(const fe_stream *s, const uint8_t *raw, int64_t N, const 
 
 template <int GM>
 void launch_fir_vec(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays, void *g,
-                    int mb, int me)
+                    int mb, int me, bool front = false)
 {
     switch (s->Tk) {
-    case 4: launch_fir_T<4, GM>(s, wk, raw, N, delays, g, mb, me); break;
-    case 8: launch_fir_T<8, GM>(s, wk, raw, N, delays, g, mb, me); break;
-    case 16: launch_fir_T<16, GM>(s, wk, raw, N, delays, g, mb, me); break;
-    case 24: launch_fir_T<24, GM>(s, wk, raw, N, delays, g, mb, me); break;
-    case 32: launch_fir_T<32, GM>(s, wk, raw, N, delays, g, mb, me); break;
+    case 4: launch_fir_T<4, GM>(s, wk, raw, N, delays, g, mb, me, front); break;
+    case 8: launch_fir_T<8, GM>(s, wk, raw, N, delays, g, mb, me, front); break;
+    case 16: launch_fir_T<16, GM>(s, wk, raw, N, delays, g, mb, me, front); break;
+    case 24: launch_fir_T<24, GM>(s, wk, raw, N, delays, g, mb, me, front); break;
+    case 32: launch_fir_T<32, GM>(s, wk, raw, N, delays, g, mb, me, front); break;
     }
+}
+
+// Whether a call's FIR also does the first FFT stage (FP32, n > 8192, up
+// to 16 taps -- with more, the FIR's window and the DFT do not fit the
+// registers together -- and not for the FIR-stage output of
+// fe_channelize_fir).
+bool fir_fronts(const fe_stream *s, bool g_out)
+{
+    return s->prec == FE_PREC_FP32 && s->n > 8192 && s->Tk <= 16 && !g_out;
 }
 
 void launch_fir(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays, float *g,
@@ -2721,7 +2801,7 @@ void launch_fir(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t 
         }
         return;
     }
-    launch_fir_vec<G_F32>(s, wk, raw, N, delays, g, mb, me);
+    launch_fir_vec<G_F32>(s, wk, raw, N, delays, g, mb, me, fir_fronts(s, g_out));
 }
 
 template <int N>
@@ -2818,11 +2898,18 @@ void launch_post_mfma(const fe_stream *s, const Work &wk, int M, const double *d
 
 template <int NL>
 void launch_post_large(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
-                       const float *gains, float *y_out, int mb, int me)
+                       const float *gains, float *y_out, int mb, int me, bool fronted)
 {
-    const int64_t fthreads = int64_t(s->A) * 2 * (me - mb) * (NL / 16);
-    hipLaunchKernelGGL(fft_front_kernel, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0, s->stream,
-                       wk.g, s->d_twf, reinterpret_cast<const float2 *>(gains), wk.gpl, NL, M, mb, me, s->A);
+    if (fronted) {
+        // the FIR did the first stage: only the gains' reordering is left
+        const int64_t total = int64_t(s->A) * 2 * NL;
+        hipLaunchKernelGGL(gains_planes_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s->stream,
+                           reinterpret_cast<const float2 *>(gains), wk.gpl, NL, total);
+    } else {
+        const int64_t fthreads = int64_t(s->A) * 2 * (me - mb) * (NL / 16);
+        hipLaunchKernelGGL(fft_front_kernel, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0, s->stream,
+                           wk.g, s->d_twf, reinterpret_cast<const float2 *>(gains), wk.gpl, NL, M, mb, me, s->A);
+    }
     // the nine rounds of each spectrum (pol) over 9 workgroups for calls of
     // under 128 spectra-pols, over 3 under 512, else one workgroup (measured
     // at 32768 channels: 128 items 0.074 -> 0.047 ms with 3 parts, 512 items
@@ -2843,14 +2930,14 @@ void launch_post_large(const fe_stream *s, const Work &wk, int M, const double *
 }
 
 void launch_post(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
-                 const float *gains, float *y_out, int mb, int me)
+                 const float *gains, float *y_out, int mb, int me, bool fronted = false)
 {
     if (s->n == 16384) {
-        launch_post_large<16384>(s, wk, M, delays, phases, gains, y_out, mb, me);
+        launch_post_large<16384>(s, wk, M, delays, phases, gains, y_out, mb, me, fronted);
         return;
     }
     if (s->n == 32768) {
-        launch_post_large<32768>(s, wk, M, delays, phases, gains, y_out, mb, me);
+        launch_post_large<32768>(s, wk, M, delays, phases, gains, y_out, mb, me, fronted);
         return;
     }
     if (s->prec == FE_PREC_FP16) {
@@ -3072,7 +3159,7 @@ fe_status channelize_impl(fe_stream *s, const uint8_t *raw, int64_t N, const dou
     if (heap)
         launch_post_heap(s, wk, M, delays, phases, gains, out);
     else if (!g_out && !fused)
-        launch_post(s, wk, M, delays, phases, gains, y_out, 0, M);
+        launch_post(s, wk, M, delays, phases, gains, y_out, 0, M, fir_fronts(s, false));
     mark(3);
     if (!g_out && !y_out && !heap)
         launch_corner_turn(s, wk, M, out);
