@@ -358,8 +358,12 @@ def test_chunking_is_invisible_and_deterministic():
     assert np.array_equal(q1, q1b)
 
 
-def test_out_of_range_delay_sets_status_and_zeroes():
-    n, T, S, M = 1024, 16, 4, 16
+@pytest.mark.parametrize("n", [1024, 16384])
+def test_out_of_range_delay_sets_status_and_zeroes(n):
+    """Invalid delays zero their spectra and raise the sticky status; at
+    16384 channels the FIR that also does the first FFT stage takes its
+    per-spectrum path for them."""
+    T, S, M = 16, 4, 16
     shape = synth.Shape(n=n, taps=T, antennas=1, samples=2 * n * M, spectra_per_heap=S)
     w = synth.make_workload(shape, 4)
     w.delays[0, 1, 5] = 128.7          # c = 129 > max_delay
