@@ -263,9 +263,13 @@ __device__ __forceinline__ void fir_block(
         X0[i] = X1[i] = 0.f;
     int c_cur = -1;
     uint32_t W[G];
-    uint32_t tail = 0;                                        // 1: this lane's last-row word is read a byte early
+    // 1: this lane's word in the region's last row would end past the
+    // region, so at this delay it reads every row's word a byte early (its
+    // pair starts at bit 2 phi <= 4 of the word, so bits 8 .. 31 still hold
+    // it) and takes its fields 8 bits lower
+    uint32_t tail = 0;
     auto issue = [&](int g0, int c, bool refill) {
-        const uint32_t voff = uint32_t(5 * (n2 * g0 - c + t)) >> 2;
+        const uint32_t voff = (uint32_t(5 * (n2 * g0 - c + t)) >> 2) - tail;
         if (refill) {
             const uint32_t v0 = voff - uint32_t((T - 1) * row_bytes);      // row g0-T+1, in the region
             gptr8 rp = (gptr8)rs;
@@ -282,7 +286,7 @@ __device__ __forceinline__ void fir_block(
             asm volatile("" : "+s"(rp));
             // rows past the region's last one (only padded outputs use them)
             // read that last row
-            W[r] = load_u32u(rp, g0 + r >= mrows - 1 ? voff - tail : voff);
+            W[r] = load_u32u(rp, voff);
             if (g0 + r + 1 < mrows)
                 rp += row_bytes;
         }
@@ -293,7 +297,9 @@ __device__ __forceinline__ void fir_block(
     // those loads counts exactly G later stores: the stores are
     // unconditional, and outputs r >= the group's count take the scalar
     // offset DROP, beyond the buffer's record count, where the hardware
-    // drops them)
+    // drops them: gfx950's range check of a raw buffer covers the scalar
+    // offset too -- a store at vector offset 0 and scalar offset past the
+    // record count writes nothing, tested inside a larger allocation)
     constexpr uint32_t DROP = 0x80000000u;
 
     // FRONT: rows row0 .. row0 + cnt - 1 (of g) from the tile, as described above
@@ -363,12 +369,11 @@ __device__ __forceinline__ void fir_block(
                 }
                 send += 64;
             }
-            // the lane whose pair ends the region at this delay reads its
-            // last-row word one byte early
             tail = (uint32_t(5 * (n2 * (mrows - 1) - c + t)) >> 2) + 4u > region_bytes ? 1u : 0u;
             const bool refill = c != c_cur;
             issue(m, c, refill);
-            const uint32_t lo = 22u - ((uint32_t(t - c) & 3u) << 1);   // first sample's field in the swapped word
+            // the first sample's field in the byte-swapped word
+            const uint32_t lo = 22u - ((uint32_t(t - c) & 3u) << 1) - 8u * tail;
             if (refill) {
 #pragma unroll
                 for (int i = 0; i < T - 1; ++i) {
@@ -381,10 +386,7 @@ __device__ __forceinline__ void fir_block(
                 float Y0[G], Y1[G];
 #pragma unroll
                 for (int r = 0; r < G; ++r) {
-                    uint32_t w = W[r];
-                    if (g0 + r >= mrows - 1)
-                        w >>= 8u * tail;
-                    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, w, 0x00010203u));
+                    const int32_t be = int32_t(__builtin_amdgcn_perm(0u, W[r], 0x00010203u));
                     Y0[r] = float(int32_t(__builtin_amdgcn_sbfe(be, lo, 10u)));
                     Y1[r] = float(int32_t(__builtin_amdgcn_sbfe(be, lo - 10u, 10u)));
                 }

@@ -289,6 +289,13 @@ CASES = [
     (16384, 16, 1, 2, 10, 2),
     (32768, 8, 2, 2, 6, 1),
     (32768, 16, 1, 2, 4, 3),
+    # two-level FFT behind each FIR form: more than 16 taps (the first
+    # radix-16 stage in a pass of its own), and 4 and 13 taps (the FIR does
+    # that stage itself)
+    (16384, 24, 1, 2, 8, 2),
+    (16384, 32, 2, 2, 6, 1),
+    (16384, 4, 1, 4, 16, 1),
+    (32768, 13, 1, 2, 6, 2),
 ]
 
 
@@ -322,7 +329,8 @@ ODD_HEAPS = [(1024, 16, 2, 3, 33, 2), (8192, 8, 1, 1, 7, 1)]
 TWO_LEVEL_SPLITS = [(16384, 8, 1, 4, 64, 1), (16384, 16, 2, 2, 128, 1)]
 
 
-@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10] + CASES[13:15] + ODD_HEAPS + TWO_LEVEL_SPLITS)
+@pytest.mark.parametrize("n,T,A,S,M,calls", CASES[:4] + CASES[8:10] + CASES[13:15] + CASES[16:]
+                         + ODD_HEAPS + TWO_LEVEL_SPLITS)
 def test_int8_matches_oracle(n, T, A, S, M, calls):
     _say("int8 n=%d T=%d A=%d S=%d M=%d calls=%d" % (n, T, A, S, M, calls))
     shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
