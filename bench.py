@@ -75,6 +75,8 @@ def kernel_names(shape: synth.Shape, prec: str, path: str = "split"):
     p = 1 if prec == "fp16" else 2
     fir = ("fir_mfma_kernel<%d, %d, %d>" % (tk, p, 0 if prec == "fp16" else 1) if path == "matrix_fir"
            else "fir_kernel<%d, %d, false>" % (next(t for t in (4, 8, 16, 24, 32) if T <= t), 1 if prec == "fp16" else 0))
+    if path == "split_folded":
+        return {"fir": fir, "post": "fft_mfma_heap_kernel<%d, %d, %d>" % (n, p, 2 if S % 2 == 0 else 1)}
     return {"fir": fir, "post": "fft_mfma_kernel<%d, %d, 0>" % (n, p), "turn": "corner_turn_kernel"}
 
 
@@ -409,11 +411,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-spectra", type=int, default=None,
                     help="spectra per antenna for the CPU baseline (default: all)")
-    ap.add_argument("--variants", default="fp16,bf16,fp16_matrix_fir,fused,split,drift",
+    ap.add_argument("--variants", default="fp16,bf16,fp16_matrix_fir,fp16_folded,fused,split,drift",
                     help="variants timed beside the FP32 path: fp16, bf16 (DFT stages on the matrix "
                          "cores, vector FIR), fp16_matrix_fir, bf16_matrix_fir (FIR on the matrix cores "
-                         "too), split, fused, split_folded (the FP32 stream on those kernel paths), drift (delays "
-                         "drifting at 1e-5 samples/sample); comma list, empty for none")
+                         "too), fp16_folded, bf16_folded (vector FIR, corner turn folded into the "
+                         "matrix-core FFT/post kernel), split, fused, split_folded (the FP32 stream on "
+                         "those kernel paths), drift (delays drifting at 1e-5 samples/sample); comma "
+                         "list, empty for none")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-stream batch measurement")
     ap.add_argument("--no-service", action="store_true", help="skip the streaming-service measurement")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -468,6 +472,11 @@ def main():
             # the reduced-precision stream with its FIR on the matrix cores
             variants[prec] = measure(fe, shape, w, sets, dev_arrays, prec[:4], args.steps, args.warmup,
                                      path="matrix_fir")
+            continue
+        if prec in ("fp16_folded", "bf16_folded"):
+            # the reduced-precision stream with the turn folded into its FFT/post kernel
+            variants[prec] = measure(fe, shape, w, sets, dev_arrays, prec[:4], args.steps, args.warmup,
+                                     path="split_folded")
             continue
         if prec in ("fused", "split", "split_folded"):
             # the same FP32 stream on another kernel path (fe_stream_set_schedule)

@@ -206,10 +206,11 @@ fe_status fe_debug_unpack10(const uint8_t *raw, int64_t first, int64_t count,
 
 /* Time the stream's launch choices on the caller's buffers (an fe_channelize
  * call's arguments; `iters` timed calls per candidate, HIP events on the
- * stream's HIP stream) and keep the fastest.  Where an FP32 stream can run
- * both the split and the fused path (fe_stream_set_schedule) each is timed,
- * and the faster kept; their results are identical bit for bit.  The FIR
- * engine of an FP16/BF16 stream is not changed (it changes the rounding).  The
+ * stream's HIP stream) and keep the fastest.  Each path the stream can run
+ * (fe_stream_set_schedule: FP32 split, split with the turn folded, fused;
+ * FP16/BF16 on the vector FIR split or folded) is timed, and the fastest
+ * kept; their results are identical bit for bit.  The FIR engine of an
+ * FP16/BF16 stream is not changed (it changes the rounding).  The
  * candidates set the FIR's schedule: for FP32 streams its run length -- how many consecutive batches
  * of spectra one workgroup filters (a batch is 64 spectra, 48 for 24 taps),
  * trading tap reloads against parallelism; for FP16/BF16 streams the chain
@@ -246,17 +247,19 @@ enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2, FE_PATH_MATRIX_FI
  *   hi + lo).  Otherwise FP16/BF16 streams filter on the vector ALUs in
  *   float32 and store the filtered samples as FP16 (FP16 streams) or float32
  *   (BF16 streams) for the matrix-core DFT stages.
- * FE_PATH_SPLIT_FOLDED (FP32 streams with n <= 8192; others run the split
- *   path): the split path without the corner-turn kernel.  Each FFT/post
- *   workgroup transforms both polarizations of one or two consecutive
+ * FE_PATH_SPLIT_FOLDED (streams with n <= 8192, FP16/BF16 ones on the
+ *   vector FIR; others run the split path): the split path without the
+ *   corner-turn kernel.  Each FFT/post workgroup (float32, or with the
+ *   matrix-core DFT stages) transforms both polarizations of one or two consecutive
  *   spectra and writes every channel's bytes straight into the heap (Sec.
  *   3.6 turns inside its post-processing kernel too): 2 bytes per sample
  *   less device-memory traffic, one launch fewer.
  * FE_PATH_AUTO: fused for FP32 streams with T <= 8 and n <= 2048; split
  *   with the turn folded for other FP32 streams with n <= 8192 whose calls
- *   give the folded kernel at least 8 workgroups per compute unit (as fast
- *   as the separate turn on MI355X, with 2 bytes per sample less traffic);
- *   else split (for FP16/BF16 streams with the vector FIR).  The schedule
+ *   give the folded kernel at least 8 workgroups per compute unit (on MI355X
+ *   as fast as the separate turn, with 2 bytes per sample less traffic);
+ *   else split (FP16/BF16 streams: their folded kernel is as fast as the
+ *   split pair, not faster; fe_stream_autotune times both).  The schedule
  *   reported for FE_PATH_AUTO is that of a call of max_samples.
  * Streams the fused path cannot run always run the split path (the setting
  * is kept).  fir_batches as in fe_stream_set_tuning; on the fused path it

@@ -895,6 +895,35 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_kern
                             delays, phases, gains, tw_all, untangle, spec8, y_out, status, M, D, mb, me);
 }
 
+// The int8 dwords q[2 f + p][i] (spectrum F0 + f, pol p; channels 2j, 2j+1,
+// j = tid + NT i) of antenna a to their places in the heaps
+// [A][M/S][n][S][2][2]: channel k's dword for one spectrum is (re, im) of pol
+// 0, then of pol 1, and its SPW spectra are contiguous (F0 is a multiple of
+// SPW, and SPW = 2 needs S even).
+template <int N, int NT, int SPW, int P>
+__device__ __forceinline__ void heap_store(const uint32_t (&q)[2 * SPW][P], int8_t *__restrict__ out, int a, int M,
+                                           int S, int F0, int tid)
+{
+    uint32_t *o = reinterpret_cast<uint32_t *>(out) + (int64_t(a) * (M / S) + F0 / S) * N * S + F0 % S;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int j = tid + NT * i;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const uint32_t sel = e == 0 ? 0x05040100u : 0x07060302u;
+            uint32_t w[SPW];
+#pragma unroll
+            for (int f = 0; f < SPW; ++f)
+                w[f] = __builtin_amdgcn_perm(q[2 * f + 1][i], q[2 * f][i], sel);
+            uint32_t *dst = o + int64_t(2 * j + e) * S;
+            if constexpr (SPW == 2)
+                *reinterpret_cast<uint2 *>(dst) = make_uint2(w[0], w[1]);
+            else
+                *dst = w[0];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel 2H: kernel 2 with the corner turn folded in (int8 output, n <= 8192).
 // One workgroup per (antenna, run of SPW consecutive spectra F0 ..): it
@@ -979,25 +1008,7 @@ __global__ __launch_bounds__(N / 16, (N / 16 >= 256 ? 4 : 1)) void fft_post_heap
         }
     }
 
-    // channel k's dword for one spectrum: (re, im) of pol 0, then of pol 1
-    uint32_t *o = reinterpret_cast<uint32_t *>(out) + (int64_t(a) * (M / S) + F0 / S) * N * S + F0 % S;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int j = int(threadIdx.x) + NT * i;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const uint32_t sel = e == 0 ? 0x05040100u : 0x07060302u;
-            uint32_t w[SPW];
-#pragma unroll
-            for (int f = 0; f < SPW; ++f)
-                w[f] = __builtin_amdgcn_perm(q[2 * f + 1][i], q[2 * f][i], sel);
-            uint32_t *dst = o + int64_t(2 * j + e) * S;
-            if constexpr (SPW == 2)
-                *reinterpret_cast<uint2 *>(dst) = make_uint2(w[0], w[1]);
-            else
-                *dst = w[0];
-        }
-    }
+    heap_store<N, NT, SPW, P>(q, out, a, M, S, F0, int(threadIdx.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -2091,30 +2102,25 @@ __device__ __forceinline__ void mfma_stages(float2 *buf, typename Mx<PREC>::op (
     }
 }
 
+// The body of kernel 2M for stream spectrum sp = (2 a + p) M + F by threads
+// tid < MPlan<N>::NT, with LDS buf (lds_len<N>), ph_hi (max(N/64, 1)) and
+// ph_lo (64).  sync: a workgroup barrier after the stage-0 operand loads,
+// before the first LDS write (for a workgroup that transformed another
+// spectrum before).  MODE OUT_REG leaves the int8 dwords in qreg.
 template <int N, int PREC, int MODE>
-__global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_kernel(
-    const void *__restrict__ g, const double *__restrict__ delays,
+__device__ __forceinline__ void fft_mfma_block(
+    int a, int p, int64_t sp, int tid, bool sync, float2 *__restrict__ buf, float2 *__restrict__ ph_hi,
+    float2 *__restrict__ ph_lo, const void *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw16, const float2 *__restrict__ untangle,
     const u32x4 *__restrict__ dft_a, uint32_t *__restrict__ spec8, float2 *__restrict__ y_out,
-    int *__restrict__ status, int M, int D, int mb, int me)
+    int *__restrict__ status, int D, uint32_t *qreg = nullptr)
 {
     using P = MPlan<N>;
     typedef typename Mx<PREC>::op op;
     constexpr int NT = P::NT;
-    constexpr int NH = N / 64;
-    __shared__ float2 buf[lds_len<N>()];
-    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
-    __shared__ float2 ph_lo[64];
-
-    const int item = xcd_logical(blockIdx.x, gridDim.x);
-    const int p = item & 1;
-    const int af = item >> 1;
-    const int a = af / (me - mb);
-    const int F = mb + af % (me - mb);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int n32 = lane & 31, h = lane >> 5;
-    const int64_t sp = (int64_t(a) * 2 + p) * M + F;
 
     // stage-0 operands straight from g: in(gam, j) = gam + (n/16) j (loaded
     // non-temporally, like the FP32 kernel: g is read once, and the int8
@@ -2165,6 +2171,8 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
     const bool ok = split_delay(delays[sp], D, c, tau);
     if (!ok && tid == 0)
         atomicOr(status, 1);
+    if (sync)
+        __syncthreads();                                    // the previous spectrum's readers are done with LDS
     constexpr float unscale = float(1 << (2 * P::S16));    // 4^stages
     phase_tables<N, NT>(ph_hi, ph_lo, phases[sp], tau, 0.5f * unscale, tid);
 
@@ -2195,7 +2203,84 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
     }
 
     post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
-                                     tid, spec8, y_out);
+                               tid, spec8, y_out, true, qreg);
+}
+
+template <int N, int PREC, int MODE>
+__global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_kernel(
+    const void *__restrict__ g, const double *__restrict__ delays,
+    const double *__restrict__ phases, const float2 *__restrict__ gains,
+    const float2 *__restrict__ tw16, const float2 *__restrict__ untangle,
+    const u32x4 *__restrict__ dft_a, uint32_t *__restrict__ spec8, float2 *__restrict__ y_out,
+    int *__restrict__ status, int M, int D, int mb, int me)
+{
+    constexpr int NH = N / 64;
+    __shared__ float2 buf[lds_len<N>()];
+    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[64];
+    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    const int p = item & 1;
+    const int af = item >> 1;
+    const int a = af / (me - mb);
+    const int F = mb + af % (me - mb);
+    const int64_t sp = (int64_t(a) * 2 + p) * M + F;
+    fft_mfma_block<N, PREC, MODE>(a, p, sp, threadIdx.x, false, buf, ph_hi, ph_lo, g, delays, phases, gains,
+                                  tw16, untangle, dft_a, spec8, y_out, status, D);
+}
+
+// Kernel 2MH: kernel 2M with the corner turn folded in (FP16/BF16, int8
+// output), organised as kernel 2H: one workgroup per (antenna, run of SPW
+// consecutive spectra) transforms and finishes both polarizations of each
+// spectrum in turn, keeping the int8 dwords in registers, and writes every
+// channel's 4 SPW bytes straight into the heap.
+template <int N, int PREC, int SPW>
+__global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_heap_kernel(
+    const void *__restrict__ g, const double *__restrict__ delays,
+    const double *__restrict__ phases, const float2 *__restrict__ gains,
+    const float2 *__restrict__ tw16, const float2 *__restrict__ untangle,
+    const u32x4 *__restrict__ dft_a, int8_t *__restrict__ out, int *__restrict__ status, int M, int D, int S)
+{
+    constexpr int NT = MPlan<N>::NT;
+    constexpr int NH = N / 64;
+    constexpr int P = N / 2 / NT;          // channel pairs per thread
+    constexpr int Q = 2 * SPW;
+    __shared__ float2 buf[lds_len<N>()];
+    __shared__ float2 ph_hi[NH < 1 ? 1 : NH];
+    __shared__ float2 ph_lo[64];
+    const int runs = M / SPW;
+    const int item = xcd_logical(blockIdx.x, gridDim.x);
+    const int a = item / runs;
+    const int F0 = (item % runs) * SPW;
+
+    uint32_t q[Q][P];
+#pragma unroll
+    for (int u = 0; u < Q; ++u)
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+            q[u][i] = 0u;
+#pragma unroll 1
+    for (int fp = 0; fp < Q; ++fp) {
+        const int f = fp >> 1, p = fp & 1;
+        // fresh copies of the thread index and table bases per pass, so that
+        // the loads derived from them are not hoisted out of the loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const float2 *tw = tw16, *ut = untangle;
+        const u32x4 *da = dft_a;
+        asm volatile("" : "+s"(tw), "+s"(ut), "+s"(da));
+        const int64_t sp = (int64_t(a) * 2 + p) * M + F0 + f;
+        uint32_t qn[P];
+        fft_mfma_block<N, PREC, OUT_REG>(a, p, sp, tid, fp > 0, buf, ph_hi, ph_lo, g, delays, phases, gains,
+                                         tw, ut, da, nullptr, nullptr, status, D, qn);
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+#pragma unroll
+            for (int u = 0; u + 1 < Q; ++u)
+                q[u][i] = q[u + 1][i];
+            q[Q - 1][i] = qn[i];
+        }
+    }
+    heap_store<N, NT, SPW, P>(q, out, a, M, S, F0, int(threadIdx.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -2838,24 +2923,68 @@ void launch_post_heap_N(const fe_stream *s, const Work &wk, int M, const double 
                            s->d_untangle, out, s->d_status, M, s->D, s->S);
 }
 
-// Whether a call of M spectra runs the folded FFT/post kernel.  FE_PATH_AUTO
-// folds only when the folded launch (a workgroup per antenna and run of one
-// or two spectra) still gives every CU eight workgroups: on fewer it is
-// slower than the split kernel's workgroup per spectrum and polarization
-// plus the separate turn.
+// Whether a call of M spectra runs the folded FFT/post kernel (kernel 2H, or
+// 2MH for FP16/BF16 streams on the vector FIR).  FE_PATH_AUTO folds FP32
+// calls only, and only when the folded launch (a workgroup per antenna and
+// run of one or two spectra) still gives every CU eight workgroups: on
+// fewer it is slower than the split kernel's workgroup per spectrum and
+// polarization plus the separate turn.  (Kernel 2MH measures as fast as 2M
+// plus the turn, not faster: 0.212 against 0.161 + 0.049 ms for FP16 at
+// 4096 channels; fe_stream_autotune times both.)
 bool heap_fold(const fe_stream *s, int M)
 {
-    if (s->prec != FE_PREC_FP32 || s->n > 8192 || fused_path(s))
+    if (s->n > 8192 || fused_path(s) || matrix_fir(s))
         return false;
     if (s->path == FE_PATH_SPLIT_FOLDED)
         return true;
+    if (s->prec != FE_PREC_FP32)
+        return false;
     const int spw = s->S % 2 == 0 ? 2 : 1;
     return s->path == FE_PATH_AUTO && int64_t(s->A) * (M / spw) >= int64_t(8) * s->cus;
+}
+
+// Kernel 2MH in place of kernels 2M and 3
+template <int N, int PREC>
+void launch_post_mfma_heap_N(const fe_stream *s, const Work &wk, int M, const double *delays,
+                             const double *phases, const float *gains, int8_t *out)
+{
+    const u32x4 *dfta = reinterpret_cast<const u32x4 *>(s->d_dfta);
+    const float2 *gn = reinterpret_cast<const float2 *>(gains);
+    if (s->S % 2 == 0)
+        hipLaunchKernelGGL((fft_mfma_heap_kernel<N, PREC, 2>), dim3(unsigned(s->A * (M / 2))),
+                           dim3(MPlan<N>::NT), 0, s->stream, wk.g, delays, phases, gn, s->d_tw16, s->d_untangle,
+                           dfta, out, s->d_status, M, s->D, s->S);
+    else
+        hipLaunchKernelGGL((fft_mfma_heap_kernel<N, PREC, 1>), dim3(unsigned(s->A * M)), dim3(MPlan<N>::NT), 0,
+                           s->stream, wk.g, delays, phases, gn, s->d_tw16, s->d_untangle, dfta, out,
+                           s->d_status, M, s->D, s->S);
+}
+
+template <int PREC>
+void launch_post_mfma_heap(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
+                           const float *gains, int8_t *out)
+{
+    switch (s->n) {
+    case 256: launch_post_mfma_heap_N<256, PREC>(s, wk, M, delays, phases, gains, out); break;
+    case 512: launch_post_mfma_heap_N<512, PREC>(s, wk, M, delays, phases, gains, out); break;
+    case 1024: launch_post_mfma_heap_N<1024, PREC>(s, wk, M, delays, phases, gains, out); break;
+    case 2048: launch_post_mfma_heap_N<2048, PREC>(s, wk, M, delays, phases, gains, out); break;
+    case 4096: launch_post_mfma_heap_N<4096, PREC>(s, wk, M, delays, phases, gains, out); break;
+    case 8192: launch_post_mfma_heap_N<8192, PREC>(s, wk, M, delays, phases, gains, out); break;
+    }
 }
 
 void launch_post_heap(const fe_stream *s, const Work &wk, int M, const double *delays, const double *phases,
                       const float *gains, int8_t *out)
 {
+    if (s->prec == FE_PREC_FP16) {
+        launch_post_mfma_heap<FE_PREC_FP16>(s, wk, M, delays, phases, gains, out);
+        return;
+    }
+    if (s->prec == FE_PREC_BF16) {
+        launch_post_mfma_heap<FE_PREC_BF16>(s, wk, M, delays, phases, gains, out);
+        return;
+    }
     switch (s->n) {
     case 256: launch_post_heap_N<256>(s, wk, M, delays, phases, gains, out); break;
     case 512: launch_post_heap_N<512>(s, wk, M, delays, phases, gains, out); break;
@@ -3524,6 +3653,9 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
             paths[npaths++] = FE_PATH_SPLIT_FOLDED;
         if (fused_eligible(s))
             paths[npaths++] = FE_PATH_FUSED;
+    } else if (!matrix_fir(s)) {
+        paths[npaths++] = FE_PATH_SPLIT;
+        paths[npaths++] = FE_PATH_SPLIT_FOLDED;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {

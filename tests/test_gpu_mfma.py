@@ -52,13 +52,14 @@ def dev(a):
 
 # Every test runs with each FIR engine of the reduced-precision streams
 # (fe_stream_set_schedule): the vector FIR in float32 storing FP16 (FP16
-# streams) or float32 (BF16 streams) filtered samples ("split", the
-# default), and the banded Toeplitz contraction on the matrix cores
-# ("matrix_fir").  The DFT-16 stages run on the matrix cores either way.
+# streams) or float32 (BF16 streams) filtered samples ("split"; with the
+# corner turn folded into the FFT/post kernel, "split_folded"), and the
+# banded Toeplitz contraction on the matrix cores ("matrix_fir").  The DFT-16
+# stages run on the matrix cores either way.
 FIR_PATH = {"now": "split"}
 
 
-@pytest.fixture(autouse=True, params=["split", "matrix_fir"])
+@pytest.fixture(autouse=True, params=["split", "split_folded", "matrix_fir"])
 def fir_engine(request):
     FIR_PATH["now"] = request.param
     _say("[fir %s]" % request.param)
@@ -263,6 +264,28 @@ def test_prequant_and_int8(prec, n, T, A, S, M, calls, every):
     q, status = gpu_run(w, 2 * n * M, prec, mode="int8")
     assert status == fe.FE_OK
     check_int8(q, ref, S, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,T,A,S,M", [(256, 16, 2, 2, 64), (1024, 16, 1, 3, 33), (2048, 8, 1, 2, 32),
+                                       (4096, 16, 2, 4, 16), (8192, 32, 1, 2, 8)])
+def test_folded_turn_bit_identical(prec, n, T, A, S, M):
+    """The FFT/post kernel with the corner turn folded in (heaps written
+    from registers) against the separate turn, over two calls: the same
+    int8 bytes, heaps of odd and even size, n = 256 (idle lanes) to 8192."""
+    if FIR_PATH["now"] != "split":
+        pytest.skip("compares two paths itself")
+    _say("folded turn %s n=%d T=%d A=%d S=%d M=%d" % (prec, n, T, A, S, M))
+    shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 61 + n + T, total=2 * shape.samples)
+    outs = {}
+    for path in ("split", "split_folded"):
+        FIR_PATH["now"] = path
+        q, status = gpu_run(w, shape.samples, prec)
+        assert status == fe.FE_OK
+        outs[path] = q
+    FIR_PATH["now"] = "split"
+    assert np.array_equal(outs["split"], outs["split_folded"])
 
 
 @pytest.mark.parametrize("prec", PRECS)
