@@ -2202,8 +2202,8 @@ __device__ __forceinline__ void fft_mfma_block(
         __syncthreads();
     }
 
-    post_spectrum<N, NT, MODE>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
-                               tid, spec8, y_out, true, qreg);
+    post_spectrum<N, NT, MODE, true>(buf, ph_hi, ph_lo, untangle, gains + (int64_t(a) * 2 + p) * N, ok, sp,
+                                     tid, spec8, y_out, true, qreg);
 }
 
 template <int N, int PREC, int MODE>
