@@ -1367,33 +1367,42 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
         // one for dsel = 0, 8)
         const bool dup = half == 1 && (dd == 0 || dd == 8);
         if (!dup) {
-            // 8 channels at a time, their table loads issued together
-            for (int k8 = 0; k8 < NS / NTS; k8 += 8) {
-                float2 wk[8], gk[8];
+            // positions kk = 2j, 2j + 1 (j = tp + NTS i) of the plane, four
+            // pairs at a time: both tables are in residue-plane order, so a
+            // pair's entries are one 16-byte load each and its two int8
+            // pairs one 4-byte store (plane dsel, coalesced)
+            for (int i0 = 0; i0 < NS / (2 * NTS); i0 += 4) {
+                float4 wk[4], gk[4];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    // both tables in residue-plane order: consecutive lanes, consecutive entries
-                    const int pos = dsel * NS + tp + NTS * (k8 + r);
-                    wk[r] = untangle[pos];
-                    gk[r] = gn[pos];
+                for (int r = 0; r < 4; ++r) {
+                    const int pos = dsel * NS + 2 * (tp + NTS * (i0 + r));
+                    wk[r] = *reinterpret_cast<const float4 *>(untangle + pos);
+                    gk[r] = *reinterpret_cast<const float4 *>(gn + pos);
                 }
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const int kk = tp + NTS * (k8 + r);
-                    const int k = dsel + 16 * kk;
-                    const int km = (NL - k) & (NL - 1);
-                    const int dm = km & 15, km2 = km >> 4;
-                    const float2 zk = bh[lds_pad(kk)];
-                    const float2 zm = buf[dm == dsel ? half : 1 - half][lds_pad(km2)];
-                    const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
-                    const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
-                    const float2 X2 = cadd(E2, cmul(wk[r], O2));
-                    const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);
-                    const float2 Y = ok ? cmul(gk[r], cmul(rot, X2)) : make_float2(0.f, 0.f);
-                    if (MODE == OUT_PREQUANT)
-                        y_out[sp * NL + k] = Y;
-                    else
-                        q16[dsel * NS + kk] = uint16_t(quant4(Y.x, Y.y, 0.f, 0.f));   // plane dsel, coalesced
+                for (int r = 0; r < 4; ++r) {
+                    const int j = tp + NTS * (i0 + r);
+                    float2 Y[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const int kk = 2 * j + e;
+                        const int k = dsel + 16 * kk;
+                        const int km = (NL - k) & (NL - 1);
+                        const int dm = km & 15, km2 = km >> 4;
+                        const float2 zk = bh[lds_pad(kk)];
+                        const float2 zm = buf[dm == dsel ? half : 1 - half][lds_pad(km2)];
+                        const float2 w = e == 0 ? make_float2(wk[r].x, wk[r].y) : make_float2(wk[r].z, wk[r].w);
+                        const float2 gg = e == 0 ? make_float2(gk[r].x, gk[r].y) : make_float2(gk[r].z, gk[r].w);
+                        const float2 E2 = make_float2(zk.x + zm.x, zk.y - zm.y);
+                        const float2 O2 = make_float2(zk.y + zm.y, zm.x - zk.x);
+                        const float2 X2 = cadd(E2, cmul(w, O2));
+                        const float2 rot = cmul(ph_hi[k >> 6], ph_lo[k & 63]);
+                        Y[e] = ok ? cmul(gg, cmul(rot, X2)) : make_float2(0.f, 0.f);
+                        if (MODE == OUT_PREQUANT)
+                            y_out[sp * NL + k] = Y[e];
+                    }
+                    if (MODE != OUT_PREQUANT)
+                        reinterpret_cast<uint32_t *>(q16)[(dsel * NS) / 2 + j] = quant4(Y[0].x, Y[0].y, Y[1].x, Y[1].y);
                 }
             }
         }

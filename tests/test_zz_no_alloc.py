@@ -47,12 +47,15 @@ def run(st, w, calls, noalloc):
 
 
 # (n, T, antennas, precision, path, samples of call 1, samples of call 2):
-# the split and fused FP32 paths, the matrix-core path, the two-level FFT,
-# and second calls shorter than the history (its assembly buffer)
+# the split, folded and fused FP32 paths, the matrix-core paths (turn
+# separate and folded), the two-level FFT, and second calls shorter than the
+# history (its assembly buffer)
 CASES = [
     (1024, 16, 2, "fp32", "split", 2 * 1024 * 64, 2 * 1024 * 16),
+    (2048, 16, 2, "fp32", "split_folded", 2 * 2048 * 32, 2 * 2048 * 8),
     (1024, 8, 1, "fp32", "fused", 2 * 1024 * 64, 2 * 1024 * 8),
     (512, 16, 1, "fp16", "auto", 2 * 512 * 96, 2 * 512 * 32),
+    (1024, 16, 1, "bf16", "split_folded", 2 * 1024 * 64, 2 * 1024 * 16),
     (16384, 16, 1, "fp32", "auto", 2 * 16384 * 32, 2 * 16384 * 16),
     (256, 16, 1, "fp32", "split", 2 * 256 * 64, 2 * 256 * 4),
 ]
