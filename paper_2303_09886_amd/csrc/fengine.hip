@@ -1969,12 +1969,21 @@ __global__ __launch_bounds__(256, 2) void fir_mfma_kernel(
 // the real 32 x 32 form of the DFT-16 matrix, scaled by 1/4 so that values
 // cannot grow out of FP16 range (the 4^stages is returned with the phase
 // table).  v_mfma_f32_32x32x16 takes K in two halves.  A leftover radix
-// (2, 4 or 8, when n is not a power of 16) runs in FP32 on the vector ALUs.
+// (2, 4 or 8, when n is not a power of 16) runs in FP32 on the vector ALUs,
+// except for FP16 at n = 8192 = 16^2 x 32, whose last stage is radix 32 on
+// the matrix cores: the real 64 x 64 form of the DFT-32 matrix (unscaled:
+// its outputs stay in FP32) as two 32-row tiles, K in four steps, 32 groups
+// (R' = 1, no twiddles) per column block.  It costs four times the matrix
+// work of a radix-16 stage, so it only matches radix 16 + the radix-2 pass
+// there (FFT/post 0.213 ms either way on 4 antennas x 2^24 samples) and
+// loses for BF16 (hi + lo: 0.287 against 0.282) and at n = 512 (FP16 0.045
+// against 0.042, BF16 0.075 against 0.055), which keep the radix-2 pass.
 // ---------------------------------------------------------------------------
 
-template <int N> struct MPlan {
-    static constexpr int S16 = N >= 4096 ? 3 : 2;           // matrix stages
-    static constexpr int RL = N >> (4 * S16);               // leftover radix: 1, 2, 4, 8
+template <int N, int PREC> struct MPlan {
+    static constexpr bool R32 = PREC == FE_PREC_FP16 && N == 8192;   // last stage radix 32 (matrix cores)
+    static constexpr int S16 = N >= 4096 ? (R32 ? 2 : 3) : 2;       // radix-16 matrix stages
+    static constexpr int RL = R32 ? 1 : N >> (4 * S16);     // leftover radix: 1, 2, 4, 8
     static constexpr int G = N / 16;                        // groups per matrix stage
     static constexpr int NT = N / 16 >= 64 ? N / 16 : 64;   // threads
     static constexpr int NW = NT / 64;
@@ -1994,19 +2003,19 @@ template <int N> __host__ __device__ constexpr int mstage_rn(int s)
 // One matrix stage reading its inputs from LDS (stages >= 1) or from the
 // registers already loaded (stage 0), writing outputs back to LDS.
 template <int N, int PREC, int S>
-__device__ __forceinline__ void mfma_stage(float2 *__restrict__ buf, typename Mx<PREC>::op (&Bh)[MPlan<N>::CPW][2],
-                                           typename Mx<PREC>::op (&Bl)[MPlan<N>::CPW][2],
+__device__ __forceinline__ void mfma_stage(float2 *__restrict__ buf, typename Mx<PREC>::op (&Bh)[MPlan<N, PREC>::CPW][2],
+                                           typename Mx<PREC>::op (&Bl)[MPlan<N, PREC>::CPW][2],
                                            const typename Mx<PREC>::op (&Ah)[2],
                                            const typename Mx<PREC>::op (&Al)[2],
                                            const float2 *__restrict__ tw16, int wave, int lane)
 {
-    using P = MPlan<N>;
+    using P = MPlan<N, PREC>;
     constexpr int RN = mstage_rn<N>(S);
     constexpr bool TWID = RN > 1;
     // FP16: stages hand their outputs to the next matrix stage as FP16 pairs
     // (exactly the next B operand); the last matrix stage writes FP32
     constexpr bool IN16 = PREC == FE_PREC_FP16 && S > 0;
-    constexpr bool OUT16 = PREC == FE_PREC_FP16 && S + 1 < P::S16;
+    constexpr bool OUT16 = PREC == FE_PREC_FP16 && (S + 1 < P::S16 || P::R32);
     uint32_t *buf32 = reinterpret_cast<uint32_t *>(buf);
     const int n32 = lane & 31, h = lane >> 5;
     if constexpr (S > 0) {
@@ -2098,21 +2107,92 @@ __device__ __forceinline__ void mfma_stage(float2 *__restrict__ buf, typename Mx
     __syncthreads();
 }
 
+// The radix-32 last stage (MPlan<N, PREC>::R32): group gam in [0, n/32) reads its
+// 32 inputs at in(gam, j) = 32 gam + j (FP16 pairs, or float32 split hi + lo
+// for BF16) and writes its DFT-32 output d to gam + (n/32) d; no twiddles.
+// A32h/A32l hold this lane's A operands [row tile][K step] of the real
+// 64 x 64 DFT-32 matrix.
+template <int N, int PREC>
+__device__ __forceinline__ void mfma_stage32(float2 *__restrict__ buf, const typename Mx<PREC>::op (&A32h)[2][4],
+                                             const typename Mx<PREC>::op (&A32l)[2][4], int wave, int lane)
+{
+    using P = MPlan<N, PREC>;
+    typedef typename Mx<PREC>::op op;
+    constexpr int G32 = N / 32;                             // groups
+    constexpr int CB32 = (G32 + 31) / 32;                   // 32-group column blocks
+    constexpr int CPW32 = (CB32 + P::NW - 1) / P::NW;       // column blocks per wave
+    constexpr bool IN16 = PREC == FE_PREC_FP16;             // the radix-16 stage before wrote FP16 pairs
+    uint32_t *buf32 = reinterpret_cast<uint32_t *>(buf);
+    const int n32 = lane & 31, h = lane >> 5;
+    op Bh[CPW32][4], Bl[CPW32][4];
+#pragma unroll
+    for (int u = 0; u < CPW32; ++u) {
+        const int cb = wave * CPW32 + u;
+        const int gam = 32 * cb + n32;
+        const bool valid = cb < CB32 && gam < G32;
+        // K step kap takes inputs j = 8 kap + 4 h + e (e < 4), interleaved (re, im)
+        const int base = 32 * gam + 4 * h;
+#pragma unroll
+        for (int kap = 0; kap < 4; ++kap) {
+            if constexpr (IN16) {
+                u32x4 w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    w[e] = valid ? buf32[lds_pad(base + 8 * kap + e)] : 0u;
+                Bh[u][kap] = __builtin_bit_cast(op, w);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float2 v = valid ? buf[lds_pad(base + 8 * kap + e)] : make_float2(0.f, 0.f);
+                    Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e, v.x);
+                    Mx<PREC>::put(Bh[u][kap], Bl[u][kap], 2 * e + 1, v.y);
+                }
+            }
+        }
+    }
+    f32x16 acc[CPW32][2];
+#pragma unroll
+    for (int u = 0; u < CPW32; ++u)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            acc[u][mt] = f32x16{};
+#pragma unroll
+            for (int kap = 0; kap < 4; ++kap)
+                acc[u][mt] = mma32<PREC>(A32h[mt][kap], A32l[mt][kap], Bh[u][kap], Bl[u][kap], acc[u][mt]);
+        }
+    __syncthreads();                                        // every input read before any output lands
+#pragma unroll
+    for (int u = 0; u < CPW32; ++u) {
+        const int cb = wave * CPW32 + u;
+        const int gam = 32 * cb + n32;
+        if (cb >= CB32 || gam >= G32)
+            continue;
+        // lane holds rows m = 8 (v / 4) + 4 h + v % 4 of both tiles: output d = m,
+        // real part in tile 0, imaginary part in tile 1
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int d = 8 * (v / 4) + 4 * h + v % 4;
+            buf[lds_pad(gam + G32 * d)] = make_float2(acc[u][0][v], acc[u][1][v]);
+        }
+    }
+    __syncthreads();
+}
+
 template <int N, int PREC, int S>
-__device__ __forceinline__ void mfma_stages(float2 *buf, typename Mx<PREC>::op (&Bh)[MPlan<N>::CPW][2],
-                                            typename Mx<PREC>::op (&Bl)[MPlan<N>::CPW][2],
+__device__ __forceinline__ void mfma_stages(float2 *buf, typename Mx<PREC>::op (&Bh)[MPlan<N, PREC>::CPW][2],
+                                            typename Mx<PREC>::op (&Bl)[MPlan<N, PREC>::CPW][2],
                                             const typename Mx<PREC>::op (&Ah)[2],
                                             const typename Mx<PREC>::op (&Al)[2],
                                             const float2 *tw16, int wave, int lane)
 {
-    if constexpr (S < MPlan<N>::S16) {
+    if constexpr (S < MPlan<N, PREC>::S16) {
         mfma_stage<N, PREC, S>(buf, Bh, Bl, Ah, Al, tw16, wave, lane);
         mfma_stages<N, PREC, S + 1>(buf, Bh, Bl, Ah, Al, tw16, wave, lane);
     }
 }
 
 // The body of kernel 2M for stream spectrum sp = (2 a + p) M + F by threads
-// tid < MPlan<N>::NT, with LDS buf (lds_len<N>), ph_hi (max(N/64, 1)) and
+// tid < MPlan<N, PREC>::NT, with LDS buf (lds_len<N>), ph_hi (max(N/64, 1)) and
 // ph_lo (64).  sync: a workgroup barrier after the stage-0 operand loads,
 // before the first LDS write (for a workgroup that transformed another
 // spectrum before).  MODE OUT_REG leaves the int8 dwords in qreg.
@@ -2125,7 +2205,7 @@ __device__ __forceinline__ void fft_mfma_block(
     const u32x4 *__restrict__ dft_a, uint32_t *__restrict__ spec8, float2 *__restrict__ y_out,
     int *__restrict__ status, int D, uint32_t *qreg = nullptr)
 {
-    using P = MPlan<N>;
+    using P = MPlan<N, PREC>;
     typedef typename Mx<PREC>::op op;
     constexpr int NT = P::NT;
     const int lane = tid & 63, wave = tid >> 6;
@@ -2187,6 +2267,22 @@ __device__ __forceinline__ void fft_mfma_block(
 
     mfma_stages<N, PREC, 0>(buf, Bh, Bl, Ah, Al, tw16, wave, lane);
 
+    if constexpr (P::R32) {
+        // the DFT-32 operands follow the DFT-16 ones in the table
+        op A32h[2][4], A32l[2][4];
+        const u32x4 *a32 = dft_a + 2 * 2 * 64;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int kap = 0; kap < 4; ++kap) {
+                A32h[mt][kap] = __builtin_bit_cast(op, a32[((mt * 4 + kap) * 2 + 0) * 64 + lane]);
+                if constexpr (Mx<PREC>::split)
+                    A32l[mt][kap] = __builtin_bit_cast(op, a32[((mt * 4 + kap) * 2 + 1) * 64 + lane]);
+                else
+                    A32l[mt][kap] = A32h[mt][kap];              // unused (no lo operand)
+            }
+        mfma_stage32<N, PREC>(buf, A32h, A32l, wave, lane);
+    }
     if constexpr (P::RL > 1) {
         // leftover radix RL in FP32: group gam reads RL gam + j, writes gam + (n/RL) d
         constexpr int GR = N / P::RL;
@@ -2216,7 +2312,7 @@ __device__ __forceinline__ void fft_mfma_block(
 }
 
 template <int N, int PREC, int MODE>
-__global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_kernel(
+__global__ __launch_bounds__((MPlan<N, PREC>::NT), (N >= 8192 ? 2 : 4)) void fft_mfma_kernel(
     const void *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw16, const float2 *__restrict__ untangle,
@@ -2243,13 +2339,13 @@ __global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_ke
 // spectrum in turn, keeping the int8 dwords in registers, and writes every
 // channel's 4 SPW bytes straight into the heap.
 template <int N, int PREC, int SPW>
-__global__ __launch_bounds__(MPlan<N>::NT, (N >= 8192 ? 2 : 4)) void fft_mfma_heap_kernel(
+__global__ __launch_bounds__((MPlan<N, PREC>::NT), (N >= 8192 ? 2 : 4)) void fft_mfma_heap_kernel(
     const void *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
     const float2 *__restrict__ tw16, const float2 *__restrict__ untangle,
     const u32x4 *__restrict__ dft_a, int8_t *__restrict__ out, int *__restrict__ status, int M, int D, int S)
 {
-    constexpr int NT = MPlan<N>::NT;
+    constexpr int NT = MPlan<N, PREC>::NT;
     constexpr int NH = N / 64;
     constexpr int P = N / 2 / NT;          // channel pairs per thread
     constexpr int Q = 2 * SPW;
@@ -2645,8 +2741,36 @@ float bf16_value(uint16_t b)
 // in split mode a second image holds the BF16 residuals.
 std::vector<uint32_t> make_dft_a(int prec)
 {
-    std::vector<uint32_t> img(size_t(2) * 2 * 64 * 4, 0u);
+    // DFT-16: [K half][hi, lo][lane][8 x 16 bit]; then DFT-32 (radix-32 last
+    // stage): [row tile][K step][hi, lo][lane][8 x 16 bit]
+    std::vector<uint32_t> img(size_t(2) * 2 * 64 * 4 + size_t(2) * 4 * 2 * 64 * 4, 0u);
     const long double pi = 3.141592653589793238462643383279503L;
+    auto store = [&](size_t image_word, int e, double val) {
+        uint16_t hi, lo = 0;
+        if (prec == FE_PREC_FP16) {
+            hi = f16_bits(float(val));
+        } else {
+            hi = bf16_bits(float(val));
+            lo = bf16_bits(float(val - double(bf16_value(hi))));
+        }
+        img[image_word] |= uint32_t(hi) << (16 * (e % 2));
+        img[image_word + 64 * 4] |= uint32_t(lo) << (16 * (e % 2));   // the lo image follows the hi one
+    };
+    const size_t base32 = size_t(2) * 2 * 64 * 4;
+    for (int mt = 0; mt < 2; ++mt)
+        for (int kap = 0; kap < 4; ++kap)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e) {
+                    // row 32 mt + m: real (mt = 0) or imaginary (mt = 1) part of output d = m;
+                    // column k: real (c = 0) or imaginary (c = 1) part of input j
+                    const int m = lane % 32, kq = lane / 32;
+                    const int k = 16 * kap + 8 * kq + e;
+                    const int j = k / 2, c = k % 2, d = m;
+                    const long double th = 2.0L * pi * (long double)((d * j) % 32) / 32.0L;
+                    const long double cs = std::cos(th), sn = std::sin(th);
+                    const double val = double(mt == 0 ? (c == 0 ? cs : sn) : (c == 0 ? -sn : cs));
+                    store(base32 + (size_t((mt * 4 + kap) * 2) * 64 + lane) * 4 + e / 2, e, val);
+                }
     for (int kap = 0; kap < 2; ++kap)
         for (int lane = 0; lane < 64; ++lane)
             for (int e = 0; e < 8; ++e) {
@@ -2673,19 +2797,21 @@ std::vector<uint32_t> make_dft_a(int prec)
 }
 
 // Matrix-stage twiddles: entry [s][gam][d] = exp(-2 pi i (gam mod R') d / R_s).
+// The table of the all-radix-16 plan; a plan ending in radix 32 uses its
+// first stages (stage s's entries depend on n and s only).
 template <int N>
 std::vector<float2> make_tw16()
 {
-    using P = MPlan<N>;
-    std::vector<float2> tw(size_t(P::S16) * P::G * 16);
+    constexpr int S16 = N >= 4096 ? 3 : 2, G = N / 16;
+    std::vector<float2> tw(size_t(S16) * G * 16);
     const long double pi = 3.141592653589793238462643383279503L;
-    for (int st = 0; st < P::S16; ++st) {
+    for (int st = 0; st < S16; ++st) {
         const int rn = mstage_rn<N>(st), rs = 16 * rn;
-        for (int gam = 0; gam < P::G; ++gam)
+        for (int gam = 0; gam < G; ++gam)
             for (int d = 0; d < 16; ++d) {
                 const int64_t q = (int64_t(gam % rn) * d) % rs;
                 const long double a = -2.0L * pi * (long double)q / (long double)rs;
-                tw[(size_t(st) * P::G + gam) * 16 + d] = make_float2(float(std::cos(a)), float(std::sin(a)));
+                tw[(size_t(st) * G + gam) * 16 + d] = make_float2(float(std::cos(a)), float(std::sin(a)));
             }
     }
     return tw;
@@ -2961,10 +3087,10 @@ void launch_post_mfma_heap_N(const fe_stream *s, const Work &wk, int M, const do
     const float2 *gn = reinterpret_cast<const float2 *>(gains);
     if (s->S % 2 == 0)
         hipLaunchKernelGGL((fft_mfma_heap_kernel<N, PREC, 2>), dim3(unsigned(s->A * (M / 2))),
-                           dim3(MPlan<N>::NT), 0, s->stream, wk.g, delays, phases, gn, s->d_tw16, s->d_untangle,
+                           dim3(MPlan<N, PREC>::NT), 0, s->stream, wk.g, delays, phases, gn, s->d_tw16, s->d_untangle,
                            dfta, out, s->d_status, M, s->D, s->S);
     else
-        hipLaunchKernelGGL((fft_mfma_heap_kernel<N, PREC, 1>), dim3(unsigned(s->A * M)), dim3(MPlan<N>::NT), 0,
+        hipLaunchKernelGGL((fft_mfma_heap_kernel<N, PREC, 1>), dim3(unsigned(s->A * M)), dim3(MPlan<N, PREC>::NT), 0,
                            s->stream, wk.g, delays, phases, gn, s->d_tw16, s->d_untangle, dfta, out,
                            s->d_status, M, s->D, s->S);
 }
@@ -3011,12 +3137,12 @@ void launch_post_mfma_N(const fe_stream *s, const Work &wk, int M, const double 
     const unsigned blocks = unsigned(s->A * (me - mb) * 2);
     const u32x4 *dfta = reinterpret_cast<const u32x4 *>(s->d_dfta);
     if (y_out)
-        hipLaunchKernelGGL((fft_mfma_kernel<N, PREC, OUT_PREQUANT>), dim3(blocks), dim3(MPlan<N>::NT), 0,
+        hipLaunchKernelGGL((fft_mfma_kernel<N, PREC, OUT_PREQUANT>), dim3(blocks), dim3(MPlan<N, PREC>::NT), 0,
                            s->stream, wk.g, delays, phases, reinterpret_cast<const float2 *>(gains),
                            s->d_tw16, s->d_untangle, dfta, wk.spec8, reinterpret_cast<float2 *>(y_out),
                            s->d_status, M, s->D, mb, me);
     else
-        hipLaunchKernelGGL((fft_mfma_kernel<N, PREC, OUT_INT8>), dim3(blocks), dim3(MPlan<N>::NT), 0,
+        hipLaunchKernelGGL((fft_mfma_kernel<N, PREC, OUT_INT8>), dim3(blocks), dim3(MPlan<N, PREC>::NT), 0,
                            s->stream, wk.g, delays, phases, reinterpret_cast<const float2 *>(gains),
                            s->d_tw16, s->d_untangle, dfta, wk.spec8, reinterpret_cast<float2 *>(y_out),
                            s->d_status, M, s->D, mb, me);
