@@ -64,6 +64,10 @@ enum {
  *                 10-bit samples are exact in FP16; the taps are scaled by a
  *                 power of two so that none falls into the FP16 subnormal
  *                 range.  Pre-quantisation error ~4e-4 relative (normwise).
+ *                 Above 8192 channels the filter runs on the vector ALUs and
+ *                 hands the two-level FFT, which runs in float32, its input
+ *                 as FP16 pairs (FP16 storage, float32 arithmetic; Sec. 6 of
+ *                 the paper suggests exactly that split).
  *   FE_PREC_BF16  the same contractions with BF16 operands, each split into
  *                 a high and a low BF16 part (three products per term); the
  *                 filtered samples pass as FP32.
@@ -74,9 +78,9 @@ enum {
 enum { FE_PREC_FP32 = 0, FE_PREC_FP16 = 1, FE_PREC_BF16 = 2 };
 
 /* Stream configuration, fixed at creation.
- *   n_channels        n: a power of two, 256 .. 32768 (FE_PREC_FP32), 256 .. 8192
- *                     (FE_PREC_FP16, FE_PREC_BF16); above 8192 the FFT runs in two
- *                     levels (a radix-16 pass in place, then n/16-point transforms)
+ *   n_channels        n: a power of two, 256 .. 32768 (FE_PREC_FP32, FE_PREC_FP16),
+ *                     256 .. 8192 (FE_PREC_BF16); above 8192 the FFT runs in two
+ *                     levels (a radix-16 pass, then n/16-point transforms)
  *   taps              T: 1 .. 32
  *   n_antennas        A >= 1; every antenna has two polarizations
  *   spectra_per_heap  S_h >= 1 (256 in the paper, Sec. 2.2)

@@ -186,6 +186,18 @@ typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
 // workgroups per CU the register budget allows (two columns' windows)
 #define FIR_WG_PER_CU(T) ((T) <= 8 ? 4 : (T) <= 16 ? 3 : 2)
 
+// One complex value as an FP16 pair (round to nearest even) and back.
+__device__ __forceinline__ uint32_t f16_pair(float2 v)
+{
+    return uint32_t(__builtin_bit_cast(uint16_t, (_Float16)v.x))
+           | (uint32_t(__builtin_bit_cast(uint16_t, (_Float16)v.y)) << 16);
+}
+__device__ __forceinline__ float2 f16_unpair(uint32_t w)
+{
+    return make_float2(float(__builtin_bit_cast(_Float16, uint16_t(w))),
+                       float(__builtin_bit_cast(_Float16, uint16_t(w >> 16))));
+}
+
 template <int GM>
 __device__ __forceinline__ void store_g2(float a, float b, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
 {
@@ -227,7 +239,7 @@ __device__ __forceinline__ void fir_block(
 {
     constexpr int G = fir_group(T);                           // spectra per group
     constexpr uint32_t ES = GM == G_F16 ? 2u : 4u;          // bytes per stored sample
-    static_assert(!FRONT || GM == G_F32, "the folded front stage runs on float32 g");
+    static_assert(!FRONT || GM == G_F32 || GM == G_F16, "the folded front stage stores float32 or FP16 pairs");
     const int cb = lb % colblocks;
     const int rest = lb / colblocks;
     const int run = rest % runs;
@@ -314,11 +326,16 @@ __device__ __forceinline__ void fir_block(
                     v[q] = fl[r][q][gl];
                 Dft<16 + 0 * T>::run(v);                      // (dependent: Dft is complete by instantiation)
                 const int gam = gbase + gl;
-                float2 *z = static_cast<float2 *>(g) + (int64_t(s) * M + row0 + r) * (n2 / 2);
+                const int64_t row = (int64_t(s) * M + row0 + r) * (n2 / 2);
                 const float2 *tw = twf + int64_t(gam) * 16;
 #pragma unroll
-                for (int d = 0; d < 16; ++d)
-                    z[gam + gpt * d] = d == 0 ? v[0] : cmul(v[d], tw[d]);
+                for (int d = 0; d < 16; ++d) {
+                    const float2 y = d == 0 ? v[0] : cmul(v[d], tw[d]);
+                    if constexpr (GM == G_F16)
+                        static_cast<uint32_t *>(g)[row + gam + gpt * d] = f16_pair(y);
+                    else
+                        static_cast<float2 *>(g)[row + gam + gpt * d] = y;
+                }
             }
         }
         __syncthreads();                                      // the tile is read
@@ -1264,6 +1281,7 @@ __global__ __launch_bounds__(N / 4) void pfb_fused_kernel(
 // spectrum) and finishes both sets of channels.
 // ---------------------------------------------------------------------------
 
+template <bool F16>
 __global__ __launch_bounds__(256) void fft_front_kernel(float *__restrict__ g, const float2 *__restrict__ twf,
                                                         const float2 *__restrict__ gains, float2 *__restrict__ gpl,
                                                         int n, int M, int mb, int me, int A)
@@ -1283,16 +1301,23 @@ __global__ __launch_bounds__(256) void fft_front_kernel(float *__restrict__ g, c
     const int gam = int(e % gpt);
     const int64_t r = e / gpt;                              // (stream, spectrum - mb)
     const int64_t sp = (r / (me - mb)) * M + mb + r % (me - mb);
+    // F16: the filtered samples and the stage's outputs as FP16 pairs
     float2 *z = reinterpret_cast<float2 *>(g) + sp * n;
+    uint32_t *z16 = reinterpret_cast<uint32_t *>(g) + sp * n;
     float2 v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-        v[j] = z[gam + gpt * j];
+        v[j] = F16 ? f16_unpair(z16[gam + gpt * j]) : z[gam + gpt * j];
     Dft<16>::run(v);
     const float2 *tw = twf + int64_t(gam) * 16;
 #pragma unroll
-    for (int d = 0; d < 16; ++d)
-        z[gam + gpt * d] = d == 0 ? v[0] : cmul(v[d], tw[d]);
+    for (int d = 0; d < 16; ++d) {
+        const float2 y = d == 0 ? v[0] : cmul(v[d], tw[d]);
+        if constexpr (F16)
+            z16[gam + gpt * d] = f16_pair(y);
+        else
+            z[gam + gpt * d] = y;
+    }
 }
 
 // fft_front_kernel's side job alone (calls whose FIR did the first stage):
@@ -1308,7 +1333,7 @@ __global__ __launch_bounds__(256) void gains_planes_kernel(const float2 *__restr
     }
 }
 
-template <int NL, int MODE>
+template <int NL, int MODE, bool F16 = false>
 __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
     const float *__restrict__ g, const double *__restrict__ delays,
     const double *__restrict__ phases, const float2 *__restrict__ gains,
@@ -1338,6 +1363,7 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
     const int half = tid / NTS, tp = tid % NTS;
     const int64_t sp = (int64_t(a) * 2 + p) * M + F;
     const float2 *u = reinterpret_cast<const float2 *>(g) + sp * NL;
+    const uint32_t *u16 = reinterpret_cast<const uint32_t *>(g) + sp * NL;   // F16: FP16 pairs
     const float2 *gn = gains + (int64_t(a) * 2 + p) * NL;
     uint16_t *q16 = reinterpret_cast<uint16_t *>(spec8) + sp * NL;
 
@@ -1354,7 +1380,7 @@ __global__ __launch_bounds__(NL / 128) void fft_post_large_kernel(
         float2 v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q)
-            v[q] = u[dsel * NS + tp + q * NTS];
+            v[q] = F16 ? f16_unpair(u16[dsel * NS + tp + q * NTS]) : u[dsel * NS + tp + q * NTS];
         Dft<16>::run(v);
 #pragma unroll
         for (int r = 0; r < 16; ++r)
@@ -2905,7 +2931,7 @@ void launch_fir_range(const fe_stream *s, const uint8_t *raw, int64_t raw_stride
             R -= B;
     const int runs = (me - mb + R - 1) / R;
     const int64_t blocks = int64_t(streams) * runs * colblocks;
-    if constexpr (GM == G_F32 && T <= 16) {
+    if constexpr ((GM == G_F32 || GM == G_F16) && T <= 16) {
         if (front) {
             hipLaunchKernelGGL((fir_kernel<T, GM, true>), dim3(unsigned(blocks)), dim3(FIR_THREADS), 0, s->stream,
                                raw, raw_stride, s->d_hist, int64_t(s->H) * 5 / 4, s->H, s->d_taps, delays, g,
@@ -2985,13 +3011,13 @@ void launch_fir_vec(const fe_stream *s, const Work &wk, const uint8_t *raw, int6
     }
 }
 
-// Whether a call's FIR also does the first FFT stage (FP32, n > 8192, up
-// to 16 taps -- with more, the FIR's window and the DFT do not fit the
-// registers together -- and not for the FIR-stage output of
-// fe_channelize_fir).
+// Whether a call's FIR also does the first FFT stage (FP32 and FP16
+// streams, n > 8192, up to 16 taps -- with more, the FIR's window and the
+// DFT do not fit the registers together -- and not for the FIR-stage output
+// of fe_channelize_fir).
 bool fir_fronts(const fe_stream *s, bool g_out)
 {
-    return s->prec == FE_PREC_FP32 && s->n > 8192 && s->Tk <= 16 && !g_out;
+    return (s->prec == FE_PREC_FP32 || s->prec == FE_PREC_FP16) && s->n > 8192 && s->Tk <= 16 && !g_out;
 }
 
 void launch_fir(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t N, const double *delays, float *g,
@@ -2999,12 +3025,13 @@ void launch_fir(const fe_stream *s, const Work &wk, const uint8_t *raw, int64_t 
 {
     if (s->prec != FE_PREC_FP32 && !matrix_fir(s)) {
         // reduced-precision streams on the vector FIR: float32 arithmetic;
-        // FP16 streams store FP16 (the matrix-core FFT's operand), BF16
-        // streams float32 (their FFT splits it into hi + lo)
+        // FP16 streams store FP16 (the matrix-core FFT's operand; above 8192
+        // channels the float32 two-level FFT's input), BF16 streams float32
+        // (their FFT splits it into hi + lo)
         if (s->prec == FE_PREC_FP16 && g_out)
             launch_fir_vec<G_F32_AS_F16>(s, wk, raw, N, delays, g, mb, me);
         else if (s->prec == FE_PREC_FP16)
-            launch_fir_vec<G_F16>(s, wk, raw, N, delays, g, mb, me);
+            launch_fir_vec<G_F16>(s, wk, raw, N, delays, g, mb, me, fir_fronts(s, g_out));
         else
             launch_fir_vec<G_F32>(s, wk, raw, N, delays, g, mb, me);
         return;
@@ -3173,8 +3200,14 @@ void launch_post_large(const fe_stream *s, const Work &wk, int M, const double *
                            reinterpret_cast<const float2 *>(gains), wk.gpl, NL, total);
     } else {
         const int64_t fthreads = int64_t(s->A) * 2 * (me - mb) * (NL / 16);
-        hipLaunchKernelGGL(fft_front_kernel, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0, s->stream,
-                           wk.g, s->d_twf, reinterpret_cast<const float2 *>(gains), wk.gpl, NL, M, mb, me, s->A);
+        if (s->prec == FE_PREC_FP16)
+            hipLaunchKernelGGL(fft_front_kernel<true>, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0,
+                               s->stream, wk.g, s->d_twf, reinterpret_cast<const float2 *>(gains), wk.gpl, NL, M,
+                               mb, me, s->A);
+        else
+            hipLaunchKernelGGL(fft_front_kernel<false>, dim3(unsigned((fthreads + 255) / 256)), dim3(256), 0,
+                               s->stream, wk.g, s->d_twf, reinterpret_cast<const float2 *>(gains), wk.gpl, NL, M,
+                               mb, me, s->A);
     }
     // the nine rounds of each spectrum (pol) over 9 workgroups for calls of
     // under 128 spectra-pols, over 3 under 512, else one workgroup (measured
@@ -3183,8 +3216,21 @@ void launch_post_large(const fe_stream *s, const Work &wk, int M, const double *
     const int items = s->A * (me - mb) * 2;
     const int rparts = items < 128 ? 9 : items < 512 ? 3 : 1;
     const unsigned blocks = unsigned(items * rparts);
-    if (y_out)
+    // FP16 streams hand the FFT its input as FP16 pairs (the two-level FFT
+    // itself runs in float32)
+    const bool f16 = s->prec == FE_PREC_FP16;
+    if (y_out && f16)
+        hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_PREQUANT, true>), dim3(blocks), dim3(NL / 128), 0,
+                           s->stream, wk.g, delays, phases, wk.gpl, s->d_tw,
+                           s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
+                           mb, me, rparts);
+    else if (y_out)
         hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_PREQUANT>), dim3(blocks), dim3(NL / 128), 0,
+                           s->stream, wk.g, delays, phases, wk.gpl, s->d_tw,
+                           s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
+                           mb, me, rparts);
+    else if (f16)
+        hipLaunchKernelGGL((fft_post_large_kernel<NL, OUT_INT8, true>), dim3(blocks), dim3(NL / 128), 0,
                            s->stream, wk.g, delays, phases, wk.gpl, s->d_tw,
                            s->d_untangle, wk.spec8, reinterpret_cast<float2 *>(y_out), s->d_status, M, s->D,
                            mb, me, rparts);
@@ -3240,7 +3286,10 @@ bool fused_eligible(const fe_stream *s)
 // (float32 arithmetic), which measured faster on MI355X -- the FIR is bound
 // by memory traffic, and its Toeplitz form spends half the contraction on
 // zeros and its staging on LDS bank conflicts.
-bool matrix_fir(const fe_stream *s) { return s->prec != FE_PREC_FP32 && s->path == FE_PATH_MATRIX_FIR; }
+bool matrix_fir(const fe_stream *s)
+{
+    return s->prec != FE_PREC_FP32 && s->path == FE_PATH_MATRIX_FIR && s->n <= 8192;
+}
 
 bool fused_path(const fe_stream *s)
 {
@@ -3477,7 +3526,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     if (cfg->precision != FE_PREC_FP32 && cfg->precision != FE_PREC_FP16 && cfg->precision != FE_PREC_BF16)
         return FE_EINVAL;
     const int n = cfg->n_channels, T = cfg->taps;
-    if (!is_pow2(n) || n < 256 || n > 32768 || (n > 8192 && cfg->precision != FE_PREC_FP32)
+    if (!is_pow2(n) || n < 256 || n > 32768 || (n > 8192 && cfg->precision == FE_PREC_BF16)
         || T < 1 || T > 32 || cfg->n_antennas < 1
         || cfg->spectra_per_heap < 1 || cfg->max_delay < 0 || cfg->max_samples <= 0)
         return FE_EINVAL;
@@ -3536,7 +3585,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     std::vector<float2> tw = twiddles_for(n);
     std::vector<float2> tw16;
     std::vector<uint32_t> dfta;
-    if (s->prec != FE_PREC_FP32) {
+    if (s->prec != FE_PREC_FP32 && n <= 8192) {
         tw16 = tw16_for(n);
         dfta = make_dft_a(s->prec);
     } else {

@@ -288,6 +288,33 @@ def test_folded_turn_bit_identical(prec, n, T, A, S, M):
     assert np.array_equal(outs["split"], outs["split_folded"])
 
 
+@pytest.mark.parametrize("n,T,A,S,M,calls", [(16384, 16, 1, 4, 16, 2), (32768, 8, 2, 2, 8, 1),
+                                             (32768, 24, 1, 2, 6, 1)])
+def test_fp16_above_8192_channels(n, T, A, S, M, calls):
+    """FP16 streams above 8192 channels: the filtered samples (already
+    through the first radix-16 stage up to 16 taps, plain above) travel as
+    FP16 pairs into the float32 two-level FFT.  Pre-quantisation normwise
+    error within the FP16 bar, int8 within 1 LSB, against the FP64 oracle."""
+    if FIR_PATH["now"] != "split":
+        pytest.skip("one FIR engine above 8192 channels")
+    _say("fp16 two-level n=%d T=%d A=%d S=%d M=%d calls=%d" % (n, T, A, S, M, calls))
+    shape = synth.Shape(n=n, taps=T, antennas=A, samples=2 * n * M, spectra_per_heap=S)
+    w = synth.make_workload(shape, 3000 + n + T, total=2 * n * M * calls)
+    ref = oracle_run(w)
+    y, status = gpu_run(w, 2 * n * M, "fp16", mode="prequant")
+    assert status == fe.FE_OK
+    check_y(y, ref["y"], "fp16 n=%d" % n)
+    q, status = gpu_run(w, 2 * n * M, "fp16")
+    assert status == fe.FE_OK
+    check_int8(q, ref, S, "fp16 n=%d" % n)
+
+
+def test_bf16_above_8192_channels_refused():
+    w = np.zeros((16, 2 * 16384), dtype=np.float32)
+    with pytest.raises(fe.FEngineError):
+        fe.Stream(16384, 16, 1, w, 2 * 16384 * 16, spectra_per_heap=16, precision="bf16")
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_stage_errors_small_config(prec):
     """Per-stage error on the 1-antenna, 2^20-sample, 1024-channel config:
