@@ -159,8 +159,9 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True, precision: str
     members (job-list kernels), as one graph launch per step with every
     member's kernels on a fork stream of its own, and as the same calls
     issued stream after stream on one HIP stream (no overlap).  With
-    `precision` fp16 or bf16 the members of up to 8192 channels run in that
-    precision (the larger ones in FP32, the only precision above 8192)."""
+    `precision` fp16 every member runs in FP16 (above 8192 channels: FP16
+    storage around the float32 two-level FFT); with bf16 the members of up
+    to 8192 channels run in BF16, the larger ones in FP32."""
     import torch
     shapes = synth.BATCH16
     streams, bufs = [], []
@@ -168,7 +169,8 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True, precision: str
         w = synth.make_workload(sh, 100 + i, delay_rate=SIDEREAL_RATE)
         M = sh.samples // (2 * sh.n)
         st = fe.Stream(sh.n, sh.taps, 1, w.weights, sh.samples, spectra_per_heap=sh.spectra_per_heap,
-                       max_delay=sh.max_delay, precision=precision if sh.n <= 8192 else "fp32")
+                       max_delay=sh.max_delay,
+                       precision=precision if (sh.n <= 8192 or precision == "fp16") else "fp32")
         out = torch.empty((1, M // sh.spectra_per_heap, sh.n, sh.spectra_per_heap, 2, 2),
                           dtype=torch.int8, device="cuda")
         b = [torch.from_numpy(w.raw).cuda(), sh.samples, torch.from_numpy(w.delays).cuda(),
@@ -222,7 +224,8 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True, precision: str
             "tuned_schedule": {"knobs": ["path (split|split_folded|fused|matrix_fir)", "fir_batches (FIR run length in batches of "
                                          "spectra, or fused workgroups per CU; 0 = per-launch default)"],
                                "per_stream": choices},
-            "precision": precision if precision == "fp32" else precision + " (members of up to 8192 channels)",
+            "precision": (precision if precision in ("fp32", "fp16")
+                          else precision + " (members of up to 8192 channels)"),
             "config": "16 single-antenna streams, channels 1024/4096/8192/32768, taps 8/16/24, "
                       "2^22..2^24 samples/pol each, heaps of 64 spectra, one HIP-graph launch per step; "
                       "grouped: FP32 split-path members through job-list kernels grouped by tap count and "
@@ -492,7 +495,7 @@ def main():
         torch.cuda.empty_cache()
         log("batch: 16 uneven streams")
         batched = measure_batch(fe, max(5, args.steps // 5), 2)
-        log("batch: 16 uneven streams, FP16 where the channel count allows")
+        log("batch: 16 uneven streams in FP16")
         batched["fp16"] = measure_batch(fe, max(5, args.steps // 5), 2, precision="fp16")
 
     streaming = None
