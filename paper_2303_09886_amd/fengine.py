@@ -177,8 +177,10 @@ class Stream:
 
     ``weights`` is a host float32 array of 2n*T taps (copied at creation).
     ``precision`` is "fp32" (default), "fp16" or "bf16" (the matrix-core
-    variants of the FIR and FFT, FE_PREC_* in the header).  ``path`` is
-    "auto" (default), "split", "fused" or "matrix_fir" (fe_stream_set_schedule).
+    variants of the FIR and FFT, FE_PREC_* in the header; above 8192 channels
+    "fp16" means FP16 storage around the float32 two-level FFT, and "bf16"
+    is refused).  ``path`` is "auto" (default), "split", "split_folded",
+    "fused" or "matrix_fir" (fe_stream_set_schedule).
     Work is enqueued on ``hip_stream`` (default: torch's current stream).
     """
 
