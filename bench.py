@@ -184,7 +184,7 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True, precision: str
             st.autotune(*b, iters=2)
     # the tuned schedule of every member: kernel path and FIR run length /
     # workgroups per CU (two knobs per stream)
-    choices = [list(st.schedule()) for st in streams]
+    choices = [list(st.schedule()) + [st.fft_parts()] for st in streams]
     total = sum(2 * sh.samples for sh in shapes)
 
     def timed(fn):
@@ -222,7 +222,9 @@ def measure_batch(fe, steps: int, warmup: int, tune: bool = True, precision: str
             "sequential_value": round(total / (seq_ms * 1e-3) / 1e9, 2),
             "streams": len(shapes), "samples_per_step": total,
             "tuned_schedule": {"knobs": ["path (split|split_folded|fused|matrix_fir)", "fir_batches (FIR run length in batches of "
-                                         "spectra, or fused workgroups per CU; 0 = per-launch default)"],
+                                         "spectra, or fused workgroups per CU; 0 = per-launch default)",
+                                         "fft_parts (above 8192 channels: workgroups per spectrum of the two-level "
+                                         "FFT's post kernel; 0 = per-call default)"],
                                "per_stream": choices},
             "precision": (precision if precision in ("fp32", "fp16")
                           else precision + " (members of up to 8192 channels)"),

@@ -221,7 +221,9 @@ fe_status fe_debug_unpack10(const uint8_t *raw, int64_t first, int64_t count,
  * length of the matrix-core FIR -- how many consecutive 256-spectrum tiles
  * one workgroup walks (its taps loaded once, each tile's rows fetched during
  * the previous tile's contraction).  Candidates: 1, 2, 4, 8, or the
- * per-launch default.
+ * per-launch default.  Then, for streams above 8192 channels, the split of
+ * the two-level FFT's post kernel (fe_stream_set_fft_parts: 1, 3 or 9
+ * workgroups per spectrum, or the per-call default) is timed the same way.
  * The timing calls advance the stream like real calls, so the stream is
  * reset (fe_stream_reset) before returning.  Synchronizes.  *choice (may be
  * NULL) receives the chosen run length (0 = per-launch default). */
@@ -233,6 +235,16 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
  * batches of spectra per run (FP32) or tiles per chain (FP16/BF16), as
  * above). */
 fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches);
+
+/* Streams above 8192 channels: the two-level FFT's post kernel transforms a
+ * spectrum's 16 sub-transforms in nine rounds (pairs d, 16 - d); `parts`
+ * workgroups share them (1 .. 9; 0 = chosen per call: 9 for calls of under
+ * 128 spectra-polarizations, 3 under 512, else 1).  Results are identical
+ * bit for bit for every value; ignored at 8192 channels and below.
+ * FE_EINVAL for parts outside 0 .. 9. */
+fe_status fe_stream_set_fft_parts(fe_stream *s, int parts);
+/* The current setting (0 = per call). */
+fe_status fe_stream_get_fft_parts(const fe_stream *s, int *parts);
 
 /* Kernels of the path (fe_stream_set_schedule). */
 enum { FE_PATH_AUTO = 0, FE_PATH_SPLIT = 1, FE_PATH_FUSED = 2, FE_PATH_MATRIX_FIR = 3, FE_PATH_SPLIT_FOLDED = 4 };

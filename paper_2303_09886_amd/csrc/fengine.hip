@@ -2654,6 +2654,7 @@ struct fe_stream {
     int fir_batches;        // FIR schedule: run length in batches of spectra (FP32) or
                             // tiles per chain (matrix-core FIR); 0: chosen per launch
     int path;               // FE_PATH_*: split or fused kernels (FP32, n <= 4096, T <= 16)
+    int fft_parts;          // n > 8192: workgroups per spectrum of the post kernel (1..9); 0: per call
     float tap_scale;        // FP16 mode: taps scaled by 2^sc on the matrix cores
     float out_scale;        // 2^-sc, applied to the FIR's FP32 result
     int64_t max_samples;
@@ -3214,7 +3215,7 @@ void launch_post_large(const fe_stream *s, const Work &wk, int M, const double *
     // at 32768 channels: 128 items 0.074 -> 0.047 ms with 3 parts, 512 items
     // 0.130 ms with one part against 0.142 with 9)
     const int items = s->A * (me - mb) * 2;
-    const int rparts = items < 128 ? 9 : items < 512 ? 3 : 1;
+    const int rparts = s->fft_parts > 0 ? s->fft_parts : items < 128 ? 9 : items < 512 ? 3 : 1;
     const unsigned blocks = unsigned(items * rparts);
     // FP16 streams hand the FFT its input as FP16 pairs (the two-level FFT
     // itself runs in float32)
@@ -3544,6 +3545,7 @@ fe_status fe_stream_create(const fe_config *cfg, void *hip_stream, fe_stream **o
     s->prec = cfg->precision;
     s->fir_batches = 0;
     s->path = FE_PATH_AUTO;
+    s->fft_parts = 0;
     s->Tk = s->prec == FE_PREC_FP32 ? kernel_taps(T) : kernel_taps_mfma(T);
     s->tap_scale = s->out_scale = 1.f;
     if (s->prec == FE_PREC_FP16) {
@@ -3875,17 +3877,62 @@ fe_status fe_stream_autotune(fe_stream *s, const uint8_t *raw, int64_t n_samples
             best_path = s->path;
         }
     }
+    s->fir_batches = st == FE_OK ? best : saved;
+    s->path = st == FE_OK ? best_path : saved_path;
+    // then, above 8192 channels, the post kernel's split of a spectrum's
+    // rounds over workgroups (results are bit-identical for every split)
+    if (st == FE_OK && s->n > 8192) {
+        static const int parts[] = {0, 1, 3, 9};
+        const int saved_parts = s->fft_parts;
+        float best_p = 3.0e38f;
+        int best_parts = saved_parts;
+        for (int c = 0; c < 4 && st == FE_OK; ++c) {
+            s->fft_parts = parts[c];
+            st = channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr);   // warm
+            if (st != FE_OK)
+                break;
+            (void)hipEventRecord(e0, s->stream);
+            for (int i = 0; i < iters && st == FE_OK; ++i)
+                st = channelize_impl(s, raw, n_samples, delays, phases, gains, out, nullptr, nullptr);
+            (void)hipEventRecord(e1, s->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                st = FE_EHIP;
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_p) {
+                best_p = ms;
+                best_parts = parts[c];
+            }
+        }
+        s->fft_parts = st == FE_OK ? best_parts : saved_parts;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     s->timing = timing;
-    s->fir_batches = st == FE_OK ? best : saved;
-    s->path = st == FE_OK ? best_path : saved_path;
     if (choice)
         *choice = s->fir_batches;
     // the timing calls advanced the stream like real calls: restart it
     if (st == FE_OK)
         st = fe_stream_reset(s);
     return st;
+}
+
+fe_status fe_stream_set_fft_parts(fe_stream *s, int parts)
+{
+    if (!s || parts < 0 || parts > 9)
+        return FE_EINVAL;
+    s->fft_parts = parts;
+    return FE_OK;
+}
+
+fe_status fe_stream_get_fft_parts(const fe_stream *s, int *parts)
+{
+    if (!s || !parts)
+        return FE_EINVAL;
+    *parts = s->fft_parts;
+    return FE_OK;
 }
 
 fe_status fe_stream_set_tuning(fe_stream *s, int fir_batches)

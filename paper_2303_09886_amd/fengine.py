@@ -84,6 +84,10 @@ def load_library(path: Optional[str] = None):
     L.fe_stream_autotune.restype = _st
     L.fe_stream_set_tuning.argtypes = [_vp, ctypes.c_int]
     L.fe_stream_set_tuning.restype = _st
+    L.fe_stream_set_fft_parts.argtypes = [_vp, ctypes.c_int]
+    L.fe_stream_set_fft_parts.restype = _st
+    L.fe_stream_get_fft_parts.argtypes = [_vp, ctypes.POINTER(ctypes.c_int)]
+    L.fe_stream_get_fft_parts.restype = _st
     L.fe_stream_set_schedule.argtypes = [_vp, ctypes.c_int, ctypes.c_int]
     L.fe_stream_set_schedule.restype = _st
     L.fe_stream_get_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -304,6 +308,15 @@ class Stream:
 
     def set_tuning(self, fir_batches: int):
         _check(load_library().fe_stream_set_tuning(self._h, int(fir_batches)), "fe_stream_set_tuning")
+
+    def set_fft_parts(self, parts: int):
+        """fe_stream_set_fft_parts (above 8192 channels; 0 = per call)."""
+        _check(load_library().fe_stream_set_fft_parts(self._h, int(parts)), "fe_stream_set_fft_parts")
+
+    def fft_parts(self) -> int:
+        p = ctypes.c_int()
+        _check(load_library().fe_stream_get_fft_parts(self._h, ctypes.byref(p)), "fe_stream_get_fft_parts")
+        return int(p.value)
 
     def set_schedule(self, path, fir_batches: int = 0):
         """fe_stream_set_schedule; ``path`` "auto", "split", "fused" or FE_PATH_*."""

@@ -198,6 +198,32 @@ def test_autotune_keeps_results(prec):
         st.close()
 
 
+def test_two_level_split_keeps_results():
+    """The two-level FFT's post kernel with a spectrum's rounds over 1, 3
+    or 9 workgroups, and as autotuned: bit-identical int8 output (16384
+    channels, 64 spectra per call: 128 spectrum-polarizations)."""
+    shape = synth.Shape(n=16384, taps=16, antennas=1, samples=2 * 16384 * 64, spectra_per_heap=16)
+    w = synth.make_workload(shape, 12)
+    raw, d, p = w.chunk(0, shape.samples)
+    args = [dev(raw), shape.samples, dev(d), dev(p), dev(w.gains)]
+    outs = []
+    for parts in (0, 1, 3, 9, "tuned"):
+        st = fe.Stream(shape.n, shape.taps, 1, w.weights, shape.samples, spectra_per_heap=16)
+        o = out_like(shape)
+        if parts == "tuned":
+            st.autotune(*args, o, iters=2)
+            _say("  autotune chose %d workgroups per spectrum (0 = per call)" % st.fft_parts())
+        else:
+            st.set_fft_parts(parts)
+            assert st.fft_parts() == parts
+        st.channelize(*args, o)
+        assert st.status() == fe.FE_OK
+        outs.append(o.cpu().numpy())
+        st.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 def test_fir_runs_longer_than_the_delay_table():
     """FIR run lengths of 64 .. 4096 spectra over 2048 spectra whose coarse
     delay steps every ~100 spectra: runs cross the 1024-spectrum segments of
