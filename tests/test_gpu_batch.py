@@ -33,8 +33,9 @@ SHAPES = [
     synth.Shape(n=8192, taps=24, antennas=1, samples=1 << 19, spectra_per_heap=16),
     synth.Shape(n=32768, taps=16, antennas=1, samples=1 << 20, spectra_per_heap=16),
     synth.Shape(n=1024, taps=16, antennas=1, samples=1 << 19, spectra_per_heap=16),
+    synth.Shape(n=32768, taps=8, antennas=1, samples=1 << 20, spectra_per_heap=16),
 ]
-PRECS = ["fp32", "fp32", "fp16", "fp32", "bf16"]
+PRECS = ["fp32", "fp32", "fp16", "fp32", "bf16", "fp16"]
 STEPS = 2
 
 
