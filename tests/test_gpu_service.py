@@ -52,7 +52,7 @@ def feeds_and_requests(n, T, S, feeds, chunks, kmax, seed):
     return works, reqs
 
 
-def alone(works, reqs, n, T, S, max_chunk):
+def alone(works, reqs, n, T, S, max_chunk, precision="fp32"):
     outs = {}
     reqs = [service.Request(r.feed, r.raw.cpu().numpy()[0] if torch.is_tensor(r.raw) else r.raw, r.n_samples,
                             r.delays.cpu().numpy()[0] if torch.is_tensor(r.delays) else r.delays,
@@ -60,7 +60,7 @@ def alone(works, reqs, n, T, S, max_chunk):
                             r.gains.cpu().numpy()[0] if torch.is_tensor(r.gains) else r.gains)
             for r in reqs]
     for f, w in enumerate(works):
-        st = fe.Stream(n, T, 1, w.weights, max_chunk, spectra_per_heap=S)
+        st = fe.Stream(n, T, 1, w.weights, max_chunk, spectra_per_heap=S, precision=precision)
         for i, r in enumerate(reqs):
             if r.feed != f:
                 continue
@@ -112,6 +112,30 @@ def test_mixed_equals_alone(realtime, own_out):
             got = r.out.numpy().reshape(ref[i].shape) if own_out else r.out
         assert got is not None and np.array_equal(got, ref[i]), i
     assert stats["peak_inflight_bytes"] <= budget
+
+
+def test_fp16_feeds_mixed_equal_alone():
+    """FP16 feeds (FP16 storage around the float32 two-level FFT at 32768
+    channels), served mixed from device memory: bit-identical to the same
+    chunks through plain FP16 streams."""
+    n, T, S = 32768, 16, 16
+    unit = 2 * n * S
+    works, reqs = feeds_and_requests(n, T, S, feeds=2, chunks=3, kmax=3, seed=11)
+    dv = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for r in reqs:
+        M = r.n_samples // (2 * n)
+        r.raw, r.delays, r.phases, r.gains = dv(r.raw[None]), dv(r.delays[None]), dv(r.phases[None]), \
+            dv(r.gains[None])
+        r.out = torch.empty((1, M // S, n, S, 2, 2), dtype=torch.int8, device="cuda")
+    max_chunk = 3 * unit
+    ref = alone(works, reqs, n, T, S, max_chunk, precision="fp16")
+    svc = service.Service(n, T, works[0].weights, feeds=2, max_chunk_samples=max_chunk,
+                          hbm_budget=3 * service.chunk_device_bytes(n, max_chunk), spectra_per_heap=S,
+                          precision="fp16")
+    svc.run(reqs, realtime=False)
+    svc.close()
+    for i, r in enumerate(reqs):
+        assert np.array_equal(r.out.cpu().numpy(), ref[i]), i
 
 
 def test_served_output_matches_oracle():
