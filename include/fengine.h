@@ -150,8 +150,9 @@ fe_status fe_channelize_prequant(fe_stream *s, const uint8_t *raw, int64_t n_sam
 /* The same call stopped after the FIR (Eq. (1)):
  *   g_out   device float32 [A][2][M][2n], the filtered samples g of every
  *           spectrum (zeros where the delay was out of range); for an
- *           FE_PREC_FP16 stream the values are the FP16-rounded ones the FFT
- *           would read.
+ *           FE_PREC_FP16 stream the values are rounded to FP16, which up to
+ *           8192 channels is what the FFT reads (above, the FFT reads the
+ *           first radix-16 stage's output rounded to FP16).
  * Updates the stream state exactly as fe_channelize does. */
 fe_status fe_channelize_fir(fe_stream *s, const uint8_t *raw, int64_t n_samples,
                             const double *delays, float *g_out);
